@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-free photoacoustic operator A and its adjoint A^T.
+
+One step = one application of A followed by one application of A^T to the
+whole synthetic input (all volumes of the workload), through the C ABI.
+Prints one JSON line (rank 0) with the A+A^T voxel x transducer pair rate,
+the roofline of the dominant kernel and the FP64 oracle's rate on the host
+cores for a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload cfg2] [--no-variants] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A+Aᵀ voxel×transducer pairs/s, closed-form FP32 vs quadrature/FP64 at rel err"
+
+# Algorithmic FLOPs per area evaluation (one quadrant of one voxel-transducer
+# pair in one fine bin), counted from the arithmetic of the common path
+# (FMA = 2, add/mul = 1, sqrt/rcp/rsq = 1; Newton refinements included).
+FLOPS_PER_EVAL = {
+    ("closed", 0): 106.0,   # planar, FP32 cancellation-free form
+    ("closed", 1): 435.0,   # cylinder, FP64 Alg. 4 edge with Legendre addition + Carlson
+}
+# per surface point of the quadrature (FP64 distance + bin test, FP32/FP64 weight)
+FLOPS_PER_POINT = 14.0
+
+PEAKS = {"f32": 157.3e12, "f64": 78.6e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    import pat_inputs as P
+    if name == "cfg1":
+        return P.config1()
+    if name == "cfg2":
+        return P.config2()
+    if name == "cfg3":
+        return P.config3()
+    if name == "cfg5":
+        return P.config5()
+    if name == "cfg4":
+        return P.config4_pgd()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_op(op, coef, y, steps, warmup, torch):
+    """Returns (ms per step, ms forward, ms adjoint) averaged over `steps`."""
+    for _ in range(warmup):
+        op.forward(coef)
+        op.adjoint(y)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record(st)
+        op.forward(coef)
+        e1.record(st)
+        op.adjoint(y)
+        e2.record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    f = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    a = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    return wall, f, a
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the operator is built and timed on a single MI355X; "
+              "multi-GPU sharding over transducers is a design note only", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_29253_amd.operator import PatOperator, build_kernel
+
+    t_build = time.perf_counter()
+    prob = build_workload(args.workload)
+    log(f"[bench] workload {prob.name}: N={prob.N} K={prob.K} L={prob.L} B={prob.coef.shape[0]} "
+        f"({time.perf_counter() - t_build:.1f}s to generate)")
+    dev = torch.device("cuda", 0)
+    kern = build_kernel(prob.phi_type, prob.kappa, prob.eir, prob.sound_speed, prob.fs, prob.U)
+    B = prob.coef.shape[0]
+    pairs = float(B) * prob.N * prob.K
+    shapes = set(int(s) for s in prob.tr.packed[:, 0])
+    shape = 1 if 1 in shapes else 0
+
+    results = {}
+
+    def run_variant(mode, prec, steps, warmup):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        op = PatOperator.from_problem(prob, mode=mode, precision=prec, max_batch=B, kernel=kern)
+        coef = torch.tensor(prob.coef, dtype=dt, device=dev)
+        y = torch.tensor(prob.y, dtype=dt, device=dev)
+        wall, f_ms, a_ms = time_op(op, coef, y, steps, warmup, torch)
+        evals = op.query(7)
+        s = op.forward(coef)
+        z = op.adjoint(y)
+        torch.cuda.synchronize()
+        out = dict(ms_per_step=wall, ms_forward=f_ms, ms_adjoint=a_ms, evals_per_volume=evals,
+                   pairs_per_s=pairs / (wall * 1e-3), s=s.double().cpu().numpy(), z=z.double().cpu().numpy())
+        op.close()
+        log(f"[bench] {mode}/{prec}: {wall:.2f} ms/step (A {f_ms:.2f} ms, A^T {a_ms:.2f} ms), "
+            f"{out['pairs_per_s']:.3e} pairs/s, {evals:.3e} area evaluations per volume")
+        return out
+
+    main_res = run_variant("closed", "fp32", args.steps, args.warmup)
+    results["closed_fp32"] = main_res
+    if not args.no_variants:
+        for mode, prec in (("closed", "fp64"), ("quadrature", "fp32"), ("quadrature", "fp64")):
+            results[f"{mode}_{prec}"] = run_variant(mode, prec, max(1, min(2, args.steps)), 1)
+
+    # ---- roofline of the dominant kernel (the area kernel of A or A^T)
+    fwd_ms, adj_ms = main_res["ms_forward"], main_res["ms_adjoint"]
+    dom_ms = max(fwd_ms, adj_ms)
+    dom_name = "k_adj_closed" if adj_ms >= fwd_ms else "k_fwd_closed"
+    flops = FLOPS_PER_EVAL[("closed", shape)] * main_res["evals_per_volume"] * B
+    area_dtype = "f64" if shape == 1 else "f32"
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    peak = PEAKS[area_dtype] / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom_name,
+                "flops_per_launch": flops, "launch_ms": round(dom_ms, 3), "area_dtype": area_dtype}
+
+    # ---- oracle on the host cores (bounded sample) and accuracy of the sample
+    cpu = None
+    rel = {}
+    if not args.no_cpu:
+        import oracle as O
+        threads = O.num_threads()
+        h, nf = O.kernel_of(prob)
+        ks = np.arange(0, prob.K, max(1, prob.K // max(1, threads)))[:max(1, threads)].astype(np.int32)
+        t = time.perf_counter()
+        s_ref = O.forward(prob, ksub=ks, kernel=(h, nf))
+        t_f = time.perf_counter() - t
+        f_pairs = float(B) * prob.N * len(ks)
+        nv = 2048
+        vs = np.linspace(0, prob.N - 1, nv).astype(np.int64)
+        t = time.perf_counter()
+        z_ref = O.adjoint(prob, vsub=vs, kernel=(h, nf))
+        t_a = time.perf_counter() - t
+        a_pairs = float(B) * nv * prob.K
+        rate = 1.0 / (t_f / f_pairs + t_a / a_pairs)
+        cpu = {"value": rate, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"A on transducers {ks.tolist()} over all {prob.N} voxels ({t_f:.1f}s) and A^T on "
+                         f"{nv} evenly spaced voxels over all {prob.K} transducers ({t_a:.1f}s), FP64 surface "
+                         f"method; rate = 1/(t_A/pair + t_AT/pair)"}
+        from numpy.linalg import norm
+        for key, r in results.items():
+            if key.startswith("closed"):
+                rel[key] = {"forward": float(norm(r["s"][:, ks, :] - s_ref) / norm(s_ref)),
+                            "adjoint": float(norm(r["z"][:, vs] - z_ref) / norm(z_ref))}
+        log(f"[bench] oracle: {rate:.3e} pairs/s on {threads} threads; rel errors {rel}")
+
+    value = main_res["pairs_per_s"]
+    variants = {k: {"ms_per_step": round(v["ms_per_step"], 3), "pairs_per_s": v["pairs_per_s"],
+                    "speedup_of_closed_fp32": round(v["ms_per_step"] / main_res["ms_per_step"], 3)}
+                for k, v in results.items()}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-io/" + area_dtype + "-area",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "voxels": prob.N, "transducers": prob.K, "samples": prob.L,
+                   "volumes": B, "U": prob.U, "area": "closed-form", "io_precision": "fp32",
+                   "shape": "cylinder" if shape == 1 else "planar"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "rel_err_vs_oracle": rel,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

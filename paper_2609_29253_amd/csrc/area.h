@@ -1,0 +1,465 @@
+// Shell areas |M_i^m| of one voxel on one transducer, device side.
+//
+// A bin m is the radial interval [r0 + m - 1, r0 + m) in units of dr = c/(U fs).
+// Both geometries use the paper's separable form (Sec. 4, Eq. separable): the
+// squared distance is psi(u) + v^2 on a parameter rectangle D, which is split
+// into at most four quadrants reflected to u, v >= 0 (Eq. uvminmax, folded
+// intervals Eq. folded_intervals for the cylinder), each of the form
+// [a, b] x [c, d].  A sweep walks the bins a quadrant touches (between its
+// nearest corner distance D_ac and farthest D_bd, Eq. closedform_rminrmax) and
+// hands each bin's area to a sink.
+//
+// Planar (Sec. 4.1): psi(u) = u^2 + x3^2, so in the plane of the rectangle the
+// shell is the annulus s0 <= u^2 + v^2 < s1 with s = r^2 - x3^2.  The area of
+// Eq. area_D_l_xi is evaluated in an equivalent form free of cancellation:
+//   2 |D^m| = int_{s0}^{s1} Theta(s) ds,
+// Theta(s) the angle subtended by the arc of radius sqrt(s) inside the
+// quadrant.  Theta = theta_hi - theta_lo, where theta_hi is acos(a/sqrt s) up to
+// the corner s_ad = a^2 + d^2 and asin(d/sqrt s) after it, theta_lo is
+// asin(c/sqrt s) up to s_bc and acos(b/sqrt s) after it.  Between these
+// breakpoints each term has the elementary antiderivative of Eq.
+// plane_primitive, rearranged as
+//   int_{s0}^{s1} acos(p/sqrt s) ds = (s1 - s0) acos(p/sqrt s1) + C,
+//   int_{s0}^{s1} asin(p/sqrt s) ds = (s1 - s0) asin(p/sqrt s1) - C,
+//   C = s0 (atan x - x) - x w0 dw,   w = sqrt(s - p^2), dw = w1 - w0,
+//   x = p dw / (p^2 + w0 w1)      (tan of the angle swept between s0 and s1),
+// so 2|D^m| = (s1 - s0) Theta(s1) + (corrections C), with Theta(s1) from one
+// atan2 of the chord between the two arc end points and every difference of
+// nearby squares taken from per-pair offsets that are exact to rounding.
+//
+// Cylinder (Sec. 4.2): psi(u) = (R - rho)^2 + 4 R rho sin^2(u/2).  Alg. 4 is
+// followed literally (triples carried from edge to edge, Eq. area_D_l_xi,
+// Eq. cyl_Il), in FP64: the cylinder's I_l is a difference of nearly equal
+// elliptic integrals.  E(beta/2, nu) - E(alpha/2, nu) is evaluated by Legendre's
+// addition theorem, E(phi) - E(psi) = E(sigma) - nu sin phi sin psi sin sigma, so
+// only one Carlson evaluation at the small amplitude sigma is needed
+// (E = s R_F(c^2, 1 - nu s^2, 1) - nu/3 s^3 R_D(c^2, 1 - nu s^2, 1), valid for
+// nu > 1 whenever nu s^2 <= 1, Lemma exact_integral).  The half angles of the
+// clamped inverse Phi (Eq. alphabeta) come from
+//   sin^2(u/2) = (s - v^2 - (R - rho)^2) / (4 R rho),
+//   1 - nu sin^2(u/2) = v^2 / (s - (R - rho)^2),
+// so arccos is never evaluated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace patop {
+
+// ---------------------------------------------------------------------------
+// small numeric helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsq64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x * r;
+    r = fma(r, fma(-h, r, 0.5), r);
+    h = 0.5 * x * r;
+    return fma(r, fma(-h, r, 0.5), r);
+}
+
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsq64(x) : 0.0; }
+
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt64(x); }
+__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float atan_t(float x) { return atanf(x); }
+__device__ __forceinline__ double atan_t(double x) { return atan(x); }
+
+template <class T>
+__device__ __forceinline__ T sdiv(T n, T d)
+{
+    return d > T(0) ? n / d : T(0);
+}
+
+// atan(x) - x for x >= 0 without cancellation: halving
+//   atan x - x = 2 (atan y - y) - x^3 / (1 + sqrt(1 + x^2))^2,  y = x / (1 + sqrt(1 + x^2)),
+// then the Taylor series of atan y - y.
+template <class T> struct AtanMx;
+
+template <> struct AtanMx<float> {
+    static __device__ __forceinline__ float eval(float x)
+    {
+        if (x > 4.0f) return atanf(x) - x;
+        float acc = 0.0f, scale = 1.0f;
+        for (int i = 0; i < 3 && x >= 0.2f; ++i) {
+            float q = 1.0f + __builtin_sqrtf(fmaf(x, x, 1.0f));
+            float iq = 1.0f / q;
+            acc = fmaf(-scale * x * x * x, iq * iq, acc);
+            x *= iq;
+            scale *= 2.0f;
+        }
+        float y = x * x;
+        float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, 1.0f / 11, -1.0f / 9), 1.0f / 7), -1.0f / 5), 1.0f / 3);
+        return fmaf(-scale * x * y, p, acc);
+    }
+};
+
+template <> struct AtanMx<double> {
+    static __device__ __forceinline__ double eval(double x)
+    {
+        if (x > 4.0) return atan(x) - x;
+        double acc = 0.0, scale = 1.0;
+        for (int i = 0; i < 4 && x >= 0.1; ++i) {
+            double q = 1.0 + sqrt64(fma(x, x, 1.0));
+            double iq = rcp64(q);
+            acc = fma(-scale * x * x * x, iq * iq, acc);
+            x *= iq;
+            scale *= 2.0;
+        }
+        double y = x * x;
+        double p = 1.0 / 23;
+        p = fma(y, p, -1.0 / 21);
+        p = fma(y, p, 1.0 / 19);
+        p = fma(y, p, -1.0 / 17);
+        p = fma(y, p, 1.0 / 15);
+        p = fma(y, p, -1.0 / 13);
+        p = fma(y, p, 1.0 / 11);
+        p = fma(y, p, -1.0 / 9);
+        p = fma(y, p, 1.0 / 7);
+        p = fma(y, p, -1.0 / 5);
+        p = fma(y, p, 1.0 / 3);
+        return fma(-scale * x * y, p, acc);
+    }
+};
+
+// correction C(p; s0, s1) of the integral of acos(p/sqrt s) over [s0, s1]
+template <class T>
+__device__ __forceinline__ T corr(T p, T s0, T dl, T w0, T w1)
+{
+    T ws = w0 + w1;
+    if (!(p > T(0)) || !(dl > T(0)) || !(ws > T(0))) return T(0);
+    T dw = dl / ws;
+    T x = p * dw / fma(p, p, w0 * w1);
+    return fma(s0, AtanMx<T>::eval(x), -x * w0 * dw);
+}
+
+// ---------------------------------------------------------------------------
+// planar quadrant
+// ---------------------------------------------------------------------------
+
+// corners: 0 = (a, c), 1 = (a, d), 2 = (b, c), 3 = (b, d)
+template <class T>
+struct PlQuad {
+    T a, b, c, d, a2, c2;
+    T gu, gv, gx;          // b^2 - a^2, d^2 - c^2, gu - gv
+    T s[4];                // in-plane squared radius of each corner
+    T e[4], twoD[4];       // r_m - D_X = (m - j_X) + e_X;  2 D_X
+    int j[4];
+    int mfirst, mlast;     // bins touched
+    T two_r0m1;            // 2 r0 - 1: (r0 + m)^2 - (r0 + m - 1)^2 = two_r0m1 + 2m
+};
+
+// FP64 per-pair setup of one planar quadrant
+template <class T>
+__device__ __forceinline__ void pl_setup(PlQuad<T>& q, double a, double b, double c, double d,
+                                         double z2, double r0)
+{
+    q.a = T(a); q.b = T(b); q.c = T(c); q.d = T(d);
+    q.a2 = T(a * a); q.c2 = T(c * c);
+    double gu = (b - a) * (b + a), gv = (d - c) * (d + c);
+    q.gu = T(gu); q.gv = T(gv); q.gx = T(gu - gv);
+    const double uu[4] = {a, a, b, b}, vv[4] = {c, d, c, d};
+#pragma unroll
+    for (int X = 0; X < 4; ++X) {
+        double s = uu[X] * uu[X] + vv[X] * vv[X];
+        double D = sqrt64(z2 + s);
+        double pos = D - r0;
+        double jj = floor(pos + 0.5);
+        q.j[X] = (int)jj;
+        q.e[X] = T(jj - pos);
+        q.twoD[X] = T(2.0 * D);
+        q.s[X] = T(s);
+        if (X == 0) q.mfirst = (int)floor(pos) + 1;
+        if (X == 3) q.mlast = (int)ceil(pos);
+    }
+    q.two_r0m1 = T(2.0 * r0 - 1.0);
+}
+
+template <class T>
+__device__ __forceinline__ T pl_qedge(const PlQuad<T>& q, int X, int m)
+{
+    T t = T(m - q.j[X]) + q.e[X];
+    return t * (t + q.twoD[X]);
+}
+
+enum { KEDGE = 0, KAC = 1, KAD = 2, KBC = 3, KBD = 4 };
+
+// Walk the bins [max(mfirst, wlo), min(mlast, whi)] of a planar quadrant; sink(m, area)
+// receives the area in dr^2 units.
+template <class T, class Sink>
+__device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, Sink& sink)
+{
+    const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
+    if (mb > me) return;
+    T Q0[4], s0;
+    int kind0;
+    bool hiS, loA;
+    if (mb == q.mfirst) {
+        Q0[0] = T(0); Q0[1] = -q.gv; Q0[2] = -q.gu; Q0[3] = -(q.gu + q.gv);
+        s0 = q.s[0];
+        kind0 = KAC;
+        hiS = false;
+        loA = false;
+    } else {
+#pragma unroll
+        for (int X = 0; X < 4; ++X) Q0[X] = pl_qedge(q, X, mb - 1);
+        s0 = Q0[0] + q.s[0];
+        kind0 = KEDGE;
+        hiS = Q0[1] > T(0);
+        loA = Q0[2] > T(0);
+    }
+    T wh0 = hiS ? sqrt_t(Q0[1] + q.a2) : sqrt_t(Q0[0] + q.c2);
+    T wl0 = loA ? sqrt_t(Q0[2] + q.c2) : sqrt_t(Q0[0] + q.a2);
+    int m = mb;
+    T acc = T(0);
+    for (int guard = 0; guard < 1 << 20; ++guard) {
+        T Qe[4];
+#pragma unroll
+        for (int X = 0; X < 4; ++X) Qe[X] = pl_qedge(q, X, m);
+        int next = KEDGE;
+        if (!hiS && Qe[1] > T(0)) next = KAD;
+        if (!loA && Qe[2] > T(0) && (next == KEDGE || q.gx < T(0))) next = KBC;
+        if (next == KEDGE && Qe[3] > T(0)) next = KBD;
+        T Q1[4], s1;
+        if (next == KEDGE) {
+#pragma unroll
+            for (int X = 0; X < 4; ++X) Q1[X] = Qe[X];
+            s1 = Qe[0] + q.s[0];
+        } else if (next == KAD) {
+            Q1[0] = q.gv; Q1[1] = T(0); Q1[2] = -q.gx; Q1[3] = -q.gu; s1 = q.s[1];
+        } else if (next == KBC) {
+            Q1[0] = q.gu; Q1[1] = q.gx; Q1[2] = T(0); Q1[3] = -q.gv; s1 = q.s[2];
+        } else {
+            Q1[0] = q.gu + q.gv; Q1[1] = q.gu; Q1[2] = q.gv; Q1[3] = T(0); s1 = q.s[3];
+        }
+        // s1 - s0 from the quantity that is exactly zero at one end
+        T dl = q.two_r0m1 + T(2 * m);
+        if (kind0 == KAC) dl = Q1[0];
+        else if (kind0 == KAD) dl = Q1[1];
+        else if (kind0 == KBC) dl = Q1[2];
+        else if (next == KAD) dl = -Q0[1];
+        else if (next == KBC) dl = -Q0[2];
+        else if (next == KBD) dl = -Q0[3];
+        // legs of the arc end points on the current hi / lo lines
+        T wh1 = hiS ? sqrt_t(Q1[1] + q.a2) : sqrt_t(Q1[0] + q.c2);
+        T wl1 = loA ? sqrt_t(Q1[2] + q.c2) : sqrt_t(Q1[0] + q.a2);
+        T xh = hiS ? wh1 : q.a, yh = hiS ? q.d : wh1;
+        T xl = loA ? q.b : wl1, yl = loA ? wl1 : q.c;
+        T chx, chy;
+        if (!hiS && !loA) {
+            chx = -sdiv(Q1[0], q.a + wl1);
+            chy = sdiv(Q1[0], wh1 + q.c);
+        } else if (!hiS) {
+            chx = q.a - q.b;
+            chy = sdiv(q.gu, wh1 + wl1);
+        } else if (!loA) {
+            chx = -sdiv(q.gv, wh1 + wl1);
+            chy = q.d - q.c;
+        } else {
+            chx = sdiv(Q1[3], wh1 + q.b);
+            chy = -sdiv(Q1[3], q.d + wl1);
+        }
+        T cross = fma(xl, chy, -yl * chx);
+        T dot = fma(xl, xh, yl * yh);
+        T th = atan2_t(cross, dot);
+        T ch = corr(hiS ? q.d : q.a, s0, dl, wh0, wh1);
+        T cl = corr(loA ? q.b : q.c, s0, dl, wl0, wl1);
+        acc += fma(dl, th, (hiS ? -ch : ch) + (loA ? -cl : cl));
+        // advance
+#pragma unroll
+        for (int X = 0; X < 4; ++X) Q0[X] = Q1[X];
+        s0 = s1;
+        kind0 = next;
+        wh0 = wh1;
+        wl0 = wl1;
+        if (next == KAD) { hiS = true; wh0 = q.a; }
+        if (next == KBC) { loA = true; wl0 = q.c; }
+        if (next == KEDGE || next == KBD) {
+            sink(m, T(0.5) * acc);
+            acc = T(0);
+            if (next == KBD || m >= me) break;
+            ++m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cylinder quadrant (FP64)
+// ---------------------------------------------------------------------------
+
+struct CyPair {
+    double R, dm, mu, inv_mu;    // radius, |R - rho|, 4 R rho, 1/mu (0 when rho = 0)
+};
+
+struct CyQuad {
+    double a, b, c, d;
+    double sa, ca, sb, cb;          // sin, cos of a/2 and b/2
+    double Dac, Dad, Dbc, Dbd, Da0, Db0;
+    double musa2, mucb2;            // mu sin^2(a/2), mu cos^2(b/2)
+    int mfirst, mlast;
+};
+
+struct CyEdge {
+    double sa, ca, da;   // alpha/2: sin, cos, Delta = sqrt(1 - nu sin^2)
+    double sb, cb, db;   // beta/2
+    double I;
+};
+
+__device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, double b, double c,
+                                         double d, double r0)
+{
+    q.a = a; q.b = b; q.c = c; q.d = d;
+    double sa, ca, sb, cb;
+    sincos(0.5 * a, &sa, &ca);
+    sincos(0.5 * b, &sb, &cb);
+    q.sa = sa; q.ca = ca; q.sb = sb; q.cb = cb;
+    double psia = fma(P.mu * sa, sa, P.dm * P.dm);
+    double psib = fma(P.mu * sb, sb, P.dm * P.dm);
+    q.Dac = sqrt64(psia + c * c);
+    q.Dad = sqrt64(psia + d * d);
+    q.Dbc = sqrt64(psib + c * c);
+    q.Dbd = sqrt64(psib + d * d);
+    q.Da0 = sqrt64(psia);
+    q.Db0 = sqrt64(psib);
+    q.musa2 = P.mu * sa * sa;
+    q.mucb2 = P.mu * cb * cb;
+    q.mfirst = (int)floor(q.Dac - r0) + 1;
+    q.mlast = (int)ceil(q.Dbd - r0);
+}
+
+// one end point of the level curve on the line v (Eq. alphabeta), half-angle form
+__device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, double r, double v,
+                                            double Dav, double Dbv, double iK, double& s, double& c,
+                                            double& dl)
+{
+    double qa = (r - Dav) * (r + Dav);          // r^2 - v^2 - psi(a)
+    if (!(qa > 0.0)) {
+        s = q.sa; c = q.ca;
+        dl = sqrt64((r - q.Da0) * (r + q.Da0) * iK);
+        return;
+    }
+    double qb = (r - Dbv) * (r + Dbv);          // r^2 - v^2 - psi(b)
+    if (!(qb < 0.0)) {
+        s = q.sb; c = q.cb;
+        dl = sqrt64((r - q.Db0) * (r + q.Db0) * iK);
+        return;
+    }
+    s = sqrt64((qa + q.musa2) * P.inv_mu);
+    c = sqrt64((q.mucb2 - qb) * P.inv_mu);
+    dl = v * sqrt64(iK);
+}
+
+// E(sigma, nu) from sin, cos and Delta of sigma (Carlson's duplication with the
+// stopping rule of Carlson 1995, tolerance 1e-13; DLMF 19.36.1-2)
+__device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu)
+{
+    double x = c * c, y = dl * dl, z = 1.0;
+    double sx = fabs(c), sy = dl, sz = 1.0;
+    double AF = (x + y + z) * (1.0 / 3.0);
+    double AD = (x + y + 3.0 * z) * 0.2;
+    double dev = fmax(fabs(AF - x), fmax(fabs(AF - y), fabs(AF - z)));
+    dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
+    const double Qf = 125.0;   // (3 * 1e-13)^(-1/6)
+    double p4 = 1.0, sumD = 0.0;
+    for (int it = 0; it < 12 && p4 * Qf * dev >= fmin(AF, AD); ++it) {
+        double lam = fma(sx, sy, fma(sx, sz, sy * sz));
+        sumD = fma(p4, rcp64(sz * (z + lam)), sumD);
+        x = 0.25 * (x + lam);
+        y = 0.25 * (y + lam);
+        z = 0.25 * (z + lam);
+        AF = 0.25 * (AF + lam);
+        AD = 0.25 * (AD + lam);
+        p4 *= 0.25;
+        sx = sqrt64(x);
+        sy = sqrt64(y);
+        sz = sqrt64(z);
+    }
+    double iAF = rcp64(AF);
+    double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
+    double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
+    double rf = (1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0)) *
+                rsq64(AF);
+    double iAD = rcp64(AD);
+    X = (AD - x) * iAD;
+    Y = (AD - y) * iAD;
+    Z = -(X + Y) * (1.0 / 3.0);
+    double XY = X * Y, Z2 = Z * Z;
+    double D2 = XY - 6.0 * Z2, D3 = (3.0 * XY - 8.0 * Z2) * Z, D4 = 3.0 * (XY - Z2) * Z2, D5 = XY * Z2 * Z;
+    double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D2 * D2 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
+                 D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0);
+    double rd = p4 * ser * iAD * rsq64(AD) + 3.0 * sumD;
+    return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
+}
+
+// Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I (Eq. cyl_Il)
+__device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
+{
+    double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
+    if (!(K > 0.0)) {
+        E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
+        return;
+    }
+    double iK = rcp64(K);
+    cy_endpoint(q, P, r, q.d, q.Dad, q.Dbd, iK, E.sa, E.ca, E.da);
+    cy_endpoint(q, P, r, q.c, q.Dac, q.Dbc, iK, E.sb, E.cb, E.db);
+    double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
+    if (!(cr > 0.0)) { E.I = 0.0; return; }
+    double nu = P.mu * iK;
+    double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
+    double idn = rcp64(den);
+    double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
+    double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
+    double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
+    double es = ellip_e_scd(ss, cs, ds, nu);
+    E.I = 2.0 * K * rsq64(K) * fma(-nu * E.sb * E.sa, ss, es);
+}
+
+// 2 atan(cr / dt) for the small angle between consecutive half angles
+__device__ __forceinline__ double twice_angle(double cr, double dt)
+{
+    if (!(cr > 0.0)) return 0.0;
+    double x = cr * rcp64(dt);
+    if (x > 0.2) return 2.0 * atan2(cr, dt);
+    double y = x * x;
+    double p = 1.0 / 23;
+    p = fma(y, p, -1.0 / 21);
+    p = fma(y, p, 1.0 / 19);
+    p = fma(y, p, -1.0 / 17);
+    p = fma(y, p, 1.0 / 15);
+    p = fma(y, p, -1.0 / 13);
+    p = fma(y, p, 1.0 / 11);
+    p = fma(y, p, -1.0 / 9);
+    p = fma(y, p, 1.0 / 7);
+    p = fma(y, p, -1.0 / 5);
+    p = fma(y, p, 1.0 / 3);
+    return 2.0 * fma(-x * y, p, x);
+}
+
+template <class Sink>
+__device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, double r0, int wlo, int whi,
+                                         Sink& sink)
+{
+    const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
+    if (mb > me) return;
+    CyEdge E0, E1;
+    cy_edge(q, P, r0 + (mb - 1), E0);
+    for (int m = mb; m <= me; ++m) {
+        cy_edge(q, P, r0 + m, E1);
+        double dal = twice_angle(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa));
+        double dbe = twice_angle(fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb));
+        // Eq. area_D_l_xi, times J0 = R
+        double area = P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
+        sink(m, area);
+        E0 = E1;
+    }
+}
+
+}  // namespace patop

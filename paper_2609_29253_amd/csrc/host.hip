@@ -1,0 +1,509 @@
+// C-ABI of the patop library: validation, device tables and launches.
+//
+// set_geometry turns the SI description of the system into device tables in
+// units of the fine radial step dr = c / (U fs): the voxel-to-transducer frame
+// transform as an affine map of the voxel indices (Sec. 4.1 and Sec. 4.2
+// frames), bounding spheres used to bound each brick's bin window
+// (Eq. rmin_rmax), the per-bin scale of Eq. ui_area, the polyphase form of the
+// convolution and down-sampling (Eq. discrete_conv, Eq. def_downsampling), and
+// the midpoint quadrature points of Alg. 2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "patop.h"
+
+using namespace patop;
+
+struct pat_ctx {
+    int device = 0;
+    bool ready = false;
+    std::string err;
+    // geometry
+    int K = 0;
+    int64_t N = 0;
+    int L = 0, U = 1, mode = 0, precision = 0, max_batch = 1;
+    bool truncated = false;
+    double work[2] = {-1.0, -1.0};   // area evaluations and pairs per volume (computed on demand)
+    size_t ws_bytes = 0;
+    LaunchPlan plan{};
+    // device allocations
+    TrDev* d_tr = nullptr;
+    int32_t* d_kperm = nullptr;
+    double* d_scale = nullptr;
+    void* d_G = nullptr;
+    double* d_qpts = nullptr;
+    double* d_qdA = nullptr;
+    double* d_f = nullptr;
+    void* d_W = nullptr;
+    double* d_z = nullptr;
+};
+
+namespace {
+
+const char* kStatusText[] = {"ok",
+                             "invalid argument",
+                             "transducer frame is not orthonormal",
+                             "invalid transducer shape parameters",
+                             "grid closer than the radial-function support to a transducer",
+                             "invalid system kernel",
+                             "geometry not set",
+                             "HIP device error",
+                             "device out of memory",
+                             "unsupported request"};
+
+pat_status fail(pat_ctx* c, pat_status st, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+void free_dev(pat_ctx* c)
+{
+    void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, &c->d_G,
+                     (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z};
+    for (void** p : ptrs) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    c->ready = false;
+    c->ws_bytes = 0;
+}
+
+struct DevGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DevGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+void cross3(const double* a, const double* b, double* o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// bounding sphere of a transducer surface
+void bounding_sphere(const pat_transducer& t, double cen[3], double& rad)
+{
+    if (t.shape == PAT_PLANAR) {
+        for (int a = 0; a < 3; ++a) cen[a] = t.c0[a];
+        rad = std::hypot(t.half_w, t.half_h);
+    } else {
+        for (int a = 0; a < 3; ++a) cen[a] = t.c0[a] + t.radius * t.e2[a];
+        rad = std::hypot(2.0 * t.radius * std::sin(0.5 * t.theta_max), t.half_len);
+    }
+}
+
+void grid_box(const pat_grid& g, double lo[3], double hi[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = g.origin[a];
+        hi[a] = g.origin[a] + (g.n[a] - 1) * g.spacing;
+    }
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+}  // namespace
+
+extern "C" {
+
+const char* pat_status_string(int32_t s)
+{
+    if (s < 0 || s > (int32_t)PAT_E_UNSUPPORTED) return "unknown status";
+    return kStatusText[s];
+}
+
+const char* pat_last_error(const pat_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pat_status pat_check_geometry(const pat_transducer* tr, int32_t K, const pat_grid* grid, double kappa,
+                              double* dist_lower)
+{
+    if (!tr || !grid || K < 1 || !(kappa > 0.0)) return PAT_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (grid->n[a] < 1) return PAT_E_ARG;
+    if (!(grid->spacing > 0.0) || !finite3(grid->origin)) return PAT_E_ARG;
+    double lo[3], hi[3];
+    grid_box(*grid, lo, hi);
+    double dmin = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const pat_transducer& t = tr[k];
+        if (t.shape != PAT_PLANAR && t.shape != PAT_CYLINDER) return PAT_E_ARG;
+        if (!finite3(t.c0) || !finite3(t.e1) || !finite3(t.e2)) return PAT_E_ARG;
+        if (std::fabs(dot3(t.e1, t.e1) - 1.0) > 1e-9 || std::fabs(dot3(t.e2, t.e2) - 1.0) > 1e-9 ||
+            std::fabs(dot3(t.e1, t.e2)) > 1e-9)
+            return PAT_E_FRAME;
+        if (t.shape == PAT_PLANAR) {
+            if (!(t.half_w > 0.0) || !(t.half_h > 0.0) || !std::isfinite(t.half_w) || !std::isfinite(t.half_h))
+                return PAT_E_SHAPE;
+        } else {
+            if (!(t.radius > 0.0) || !(t.theta_max > 0.0) || !(t.theta_max < 0.5 * M_PI) || !(t.half_len > 0.0) ||
+                !std::isfinite(t.radius) || !std::isfinite(t.half_len))
+                return PAT_E_SHAPE;
+        }
+        double cen[3], rad;
+        bounding_sphere(t, cen, rad);
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double o = std::max(0.0, std::max(lo[a] - cen[a], cen[a] - hi[a]));
+            d2 += o * o;
+        }
+        dmin = std::min(dmin, std::sqrt(d2) - rad);
+    }
+    if (dist_lower) *dist_lower = dmin;
+    // Assumption 1(iii): dist_min >= kappa (checked on a lower bound of dist_min)
+    if (!(dmin >= kappa)) return PAT_E_SEPARATION;
+    return PAT_OK;
+}
+
+pat_status pat_create(pat_ctx** out, int32_t device)
+{
+    if (!out) return PAT_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return PAT_E_DEVICE;
+    pat_ctx* c = new (std::nothrow) pat_ctx();
+    if (!c) return PAT_E_OOM;
+    c->device = device;
+    *out = c;
+    return PAT_OK;
+}
+
+void pat_destroy(pat_ctx* c)
+{
+    if (!c) return;
+    {
+        DevGuard g(c->device);
+        if (g.ok) (void)hipDeviceSynchronize();
+        free_dev(c);
+    }
+    delete c;
+}
+
+pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, const pat_grid* grid,
+                            const pat_kernel* kernel, const pat_params* prm)
+{
+    if (!c) return PAT_E_ARG;
+    DevGuard guard(c->device);
+    if (!guard.ok) return fail(c, PAT_E_DEVICE, "hipSetDevice failed");
+    (void)hipDeviceSynchronize();
+    free_dev(c);
+    if (!tr || !grid || !kernel || !prm || K < 1) return fail(c, PAT_E_ARG, "null argument or K < 1");
+    const pat_params& p = *prm;
+    if (!(p.sound_speed > 0.0) || !(p.fs > 0.0) || !(p.t0 >= 0.0) || !std::isfinite(p.t0) || p.L < 1 || p.U < 1 ||
+        p.max_batch < 1 || p.flags != 0)
+        return fail(c, PAT_E_ARG, "invalid sampling parameters");
+    if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE)
+        return fail(c, PAT_E_ARG, "invalid area_mode");
+    if (p.precision != PAT_FP32 && p.precision != PAT_FP64) return fail(c, PAT_E_ARG, "invalid precision");
+    if (p.area_mode == PAT_AREA_QUADRATURE &&
+        (p.quad_n1 < 1 || p.quad_n2 < 1 || (int64_t)p.quad_n1 * p.quad_n2 > (1 << 16)))
+        return fail(c, PAT_E_ARG, "invalid quadrature size");
+    if (!kernel->h || kernel->len < 1 || kernel->len > (1 << 24) || !(kernel->kappa > 0.0))
+        return fail(c, PAT_E_KERNEL, "empty kernel or kappa <= 0");
+    for (int64_t i = 0; i < kernel->len; ++i)
+        if (!std::isfinite(kernel->h[i])) return fail(c, PAT_E_KERNEL, "non-finite kernel tap");
+    double dlow = 0.0;
+    pat_status st = pat_check_geometry(tr, K, grid, kernel->kappa, &dlow);
+    if (st != PAT_OK) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "geometry check failed (%s), distance lower bound %.6g m", pat_status_string(st),
+                 dlow);
+        return fail(c, st, buf);
+    }
+    const int64_t N = grid->n[0] * grid->n[1] * grid->n[2];
+    if (N >= (int64_t)1 << 31) return fail(c, PAT_E_UNSUPPORTED, "more than 2^31 voxels");
+
+    const double dr = p.sound_speed / (p.U * p.fs);
+    const double r0 = p.t0 * p.U * p.fs;
+    const int64_t nf = kernel->n_first, nl = kernel->n_first + kernel->len - 1;
+    const int64_t Mlo = 1 - nl, Mhi = (int64_t)p.U * p.L - nf;
+    const int64_t Mcount = Mhi - Mlo + 1;
+    if (Mcount < 1 || Mhi > (1 << 30) || Mlo < -(1 << 30)) return fail(c, PAT_E_UNSUPPORTED, "time axis too long");
+
+    // ---- transducer table (dr units)
+    std::vector<TrDev> T(K);
+    std::vector<int32_t> perm;
+    int nplan = 0, ncyl = 0;
+    double glo[3], ghi[3];
+    grid_box(*grid, glo, ghi);
+    double dmax_all = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const pat_transducer& t = tr[k];
+        double n3[3];
+        cross3(t.e1, t.e2, n3);
+        const double* ax[3];
+        if (t.shape == PAT_PLANAR) { ax[0] = t.e1; ax[1] = t.e2; ax[2] = n3; ++nplan; }
+        else { ax[0] = t.e2; ax[1] = n3; ax[2] = t.e1; ++ncyl; }
+        TrDev& d = T[k];
+        std::memset(&d, 0, sizeof d);
+        double o[3] = {grid->origin[0] - t.c0[0], grid->origin[1] - t.c0[1], grid->origin[2] - t.c0[2]};
+        for (int a = 0; a < 3; ++a) {
+            d.base[a] = dot3(o, ax[a]) / dr;
+            for (int q = 0; q < 3; ++q) d.g[a][q] = grid->spacing * ax[a][q] / dr;
+        }
+        double cen[3], rad;
+        bounding_sphere(t, cen, rad);
+        for (int a = 0; a < 3; ++a) d.cen[a] = cen[a] / dr;
+        d.rad = rad / dr;
+        if (t.shape == PAT_PLANAR) { d.p[0] = t.half_w / dr; d.p[1] = t.half_h / dr; }
+        else { d.p[0] = t.radius / dr; d.p[1] = t.theta_max; d.p[2] = t.half_len / dr; }
+        d.shape = t.shape;
+        double far2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double f = std::max(std::fabs(glo[a] - cen[a]), std::fabs(ghi[a] - cen[a]));
+            far2 += f * f;
+        }
+        dmax_all = std::max(dmax_all, std::sqrt(far2) + rad);
+    }
+    for (int k = 0; k < K; ++k)
+        if (T[k].shape == PAT_PLANAR) perm.push_back(k);
+    for (int k = 0; k < K; ++k)
+        if (T[k].shape == PAT_CYLINDER) perm.push_back(k);
+    c->truncated = (int64_t)std::ceil(dmax_all / dr - r0) + nl > (int64_t)p.U * p.L;
+
+    // ---- per-bin scale (Eq. ui_area: U fs / (c tau_{m-1/2}); point method: U fs)
+    std::vector<double> scale(Mcount);
+    for (int64_t i = 0; i < Mcount; ++i) {
+        if (p.area_mode == PAT_AREA_CLOSED) {
+            double rm = r0 + (double)(Mlo + i) - 0.5;   // c tau_{m-1/2} / dr
+            scale[i] = rm > 0.0 ? p.U * p.fs * dr / rm : 0.0;
+        } else {
+            scale[i] = p.U * p.fs * dr;
+        }
+    }
+    // ---- polyphase filter G[j] = 1/U sum_{l'=1..U} h[j + l'],  j in [nf - U, nl - 1]
+    const int jlo = (int)(nf - p.U), jcnt = (int)(kernel->len + p.U - 1);
+    std::vector<double> G(jcnt, 0.0);
+    for (int jj = 0; jj < jcnt; ++jj) {
+        double acc = 0.0;
+        for (int lp = 1; lp <= p.U; ++lp) {
+            int64_t n = (int64_t)jlo + jj + lp;
+            if (n >= nf && n <= nl) acc += kernel->h[n - nf];
+        }
+        G[jj] = acc / p.U;
+    }
+    // ---- quadrature points (midpoint tensor rule, barycentres of equal cells)
+    std::vector<double> qp, qdA;
+    int Q = 0;
+    if (p.area_mode == PAT_AREA_QUADRATURE) {
+        Q = p.quad_n1 * p.quad_n2;
+        qp.resize((size_t)K * Q * 3);
+        qdA.resize(K);
+        for (int k = 0; k < K; ++k) {
+            const pat_transducer& t = tr[k];
+            double n3[3];
+            cross3(t.e1, t.e2, n3);
+            double* P = qp.data() + (size_t)k * Q * 3;
+            if (t.shape == PAT_PLANAR) {
+                double du = 2.0 * t.half_w / p.quad_n1, dv = 2.0 * t.half_h / p.quad_n2;
+                qdA[k] = du * dv / (dr * dr);
+                for (int a = 0; a < p.quad_n1; ++a)
+                    for (int b = 0; b < p.quad_n2; ++b) {
+                        double u = -t.half_w + (a + 0.5) * du, v = -t.half_h + (b + 0.5) * dv;
+                        for (int q = 0; q < 3; ++q)
+                            P[3 * (a * p.quad_n2 + b) + q] = (t.c0[q] + u * t.e1[q] + v * t.e2[q]) / dr;
+                    }
+            } else {
+                double dth = 2.0 * t.theta_max / p.quad_n1, dz = 2.0 * t.half_len / p.quad_n2;
+                qdA[k] = t.radius * dth * dz / (dr * dr);
+                for (int a = 0; a < p.quad_n1; ++a)
+                    for (int b = 0; b < p.quad_n2; ++b) {
+                        double th = -t.theta_max + (a + 0.5) * dth, z = -t.half_len + (b + 0.5) * dz;
+                        double cs = std::cos(th), sn = std::sin(th);
+                        for (int q = 0; q < 3; ++q)
+                            P[3 * (a * p.quad_n2 + b) + q] =
+                                (t.c0[q] + t.radius * cs * t.e2[q] + t.radius * sn * n3[q] + z * t.e1[q]) / dr;
+                    }
+            }
+        }
+    }
+
+    // ---- work decomposition
+    const int nbx = (int)((grid->n[0] + kBrickX - 1) / kBrickX);
+    const int nby = (int)((grid->n[1] + kBrickY - 1) / kBrickY);
+    const int nbz = (int)((grid->n[2] + kBrickZ - 1) / kBrickZ);
+    const int nbricks = nbx * nby * nbz;
+    const int target_wg = 4096;
+
+    // ---- device allocations
+    const size_t rs = p.precision == PAT_FP64 ? sizeof(double) : sizeof(float);
+    const size_t fbytes = (size_t)p.max_batch * K * Mcount * sizeof(double);
+    const size_t wbytes = (size_t)p.max_batch * K * Mcount * rs;
+    const size_t zbytes = (size_t)p.max_batch * N * sizeof(double);
+    auto dmalloc = [&](void** ptr, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 8;
+        return hipMalloc(ptr, bytes) == hipSuccess;
+    };
+    if (!dmalloc((void**)&c->d_tr, sizeof(TrDev) * K) || !dmalloc((void**)&c->d_kperm, sizeof(int32_t) * K) ||
+        !dmalloc((void**)&c->d_scale, sizeof(double) * Mcount) || !dmalloc(&c->d_G, rs * jcnt) ||
+        !dmalloc((void**)&c->d_f, fbytes) || !dmalloc(&c->d_W, wbytes) || !dmalloc((void**)&c->d_z, zbytes) ||
+        (Q > 0 && (!dmalloc((void**)&c->d_qpts, sizeof(double) * qp.size()) ||
+                   !dmalloc((void**)&c->d_qdA, sizeof(double) * K)))) {
+        (void)hipGetLastError();
+        free_dev(c);
+        return fail(c, PAT_E_OOM, "device allocation failed");
+    }
+    c->ws_bytes = fbytes + wbytes + zbytes;
+    hipError_t e = hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up(c->d_tr, T.data(), sizeof(TrDev) * K);
+    up(c->d_kperm, perm.data(), sizeof(int32_t) * K);
+    up(c->d_scale, scale.data(), sizeof(double) * Mcount);
+    if (p.precision == PAT_FP64) {
+        up(c->d_G, G.data(), sizeof(double) * jcnt);
+    } else {
+        std::vector<float> Gf(G.begin(), G.end());
+        up(c->d_G, Gf.data(), sizeof(float) * jcnt);
+    }
+    if (Q > 0) {
+        up(c->d_qpts, qp.data(), sizeof(double) * qp.size());
+        up(c->d_qdA, qdA.data(), sizeof(double) * K);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        std::string msg = std::string("upload failed: ") + hipGetErrorString(e);
+        free_dev(c);
+        return fail(c, PAT_E_DEVICE, msg);
+    }
+
+    // ---- launch plan
+    LaunchPlan& Lp = c->plan;
+    std::memset(&Lp, 0, sizeof Lp);
+    KParams& B = Lp.base;
+    B.tr = c->d_tr;
+    B.K = K;
+    for (int a = 0; a < 3; ++a) {
+        B.n[a] = grid->n[a];
+        B.origin[a] = grid->origin[a] / dr;
+    }
+    B.w = grid->spacing / dr;
+    B.r0 = r0;
+    B.Mlo = Mlo;
+    B.Mcount = Mcount;
+    B.nbx = nbx;
+    B.nby = nby;
+    B.nbz = nbz;
+    B.N = N;
+    B.qpts = c->d_qpts;
+    B.qdA = c->d_qdA;
+    B.Q = Q;
+    Lp.ngroups = 0;
+    int off = 0;
+    for (int s = 0; s < 2; ++s) {
+        int nk = s == 0 ? nplan : ncyl;
+        if (nk == 0) continue;
+        ShapeGroup& Gp = Lp.groups[Lp.ngroups++];
+        Gp.shape = s;
+        Gp.kperm = c->d_kperm + off;
+        Gp.nk = nk;
+        int nchunks = std::max(1, std::min(nk, (target_wg + nbricks - 1) / nbricks));
+        Gp.kchunk_fwd = (nk + nchunks - 1) / nchunks;
+        Gp.kchunk_adj = Gp.kchunk_fwd;
+        off += nk;
+    }
+    Lp.nbricks = nbricks;
+    Lp.mode = p.area_mode;
+    Lp.fp64 = p.precision == PAT_FP64;
+    Lp.U = p.U;
+    Lp.L = p.L;
+    Lp.jlo = jlo;
+    Lp.jcnt = jcnt;
+    Lp.G = c->d_G;
+    Lp.scale = c->d_scale;
+    Lp.f = c->d_f;
+    Lp.W = c->d_W;
+    Lp.z64 = c->d_z;
+
+    c->K = K;
+    c->N = N;
+    c->L = p.L;
+    c->U = p.U;
+    c->mode = p.area_mode;
+    c->precision = p.precision;
+    c->max_batch = p.max_batch;
+    c->work[0] = c->work[1] = -1.0;
+    c->ready = true;
+    c->err.clear();
+    return PAT_OK;
+}
+
+static pat_status run(pat_ctx* c, const void* in, void* out, int32_t batch, void* stream, bool fwd)
+{
+    if (!c) return PAT_E_ARG;
+    if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
+    if (!in || !out || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
+    DevGuard guard(c->device);
+    if (!guard.ok) return fail(c, PAT_E_DEVICE, "hipSetDevice failed");
+    hipError_t e = fwd ? launch_forward(c->plan, in, out, batch, (hipStream_t)stream)
+                       : launch_adjoint(c->plan, in, out, batch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(c, PAT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return PAT_OK;
+}
+
+pat_status pat_forward(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
+{
+    return run(c, coef, signal, batch, stream, true);
+}
+
+pat_status pat_adjoint(pat_ctx* c, const void* signal, void* coef, int32_t batch, void* stream)
+{
+    return run(c, signal, coef, batch, stream, false);
+}
+
+pat_status pat_query(const pat_ctx* c, int32_t what, double* out)
+{
+    if (!out) return PAT_E_ARG;
+    if (what == 6) { *out = PATOP_ABI_VERSION; return PAT_OK; }
+    if (!c) return PAT_E_ARG;
+    if (!c->ready) return PAT_E_STATE;
+    switch (what) {
+    case 0: *out = c->K; return PAT_OK;
+    case 1: *out = (double)c->N; return PAT_OK;
+    case 2: *out = (double)c->plan.base.Mcount; return PAT_OK;
+    case 3: *out = (double)c->plan.base.Mlo; return PAT_OK;
+    case 4: *out = c->truncated ? 1.0 : 0.0; return PAT_OK;
+    case 5: *out = (double)c->ws_bytes; return PAT_OK;
+    case 7:
+    case 8: {
+        pat_ctx* m = const_cast<pat_ctx*>(c);
+        if (m->work[0] < 0.0) {
+            DevGuard guard(m->device);
+            unsigned long long* d = nullptr;
+            unsigned long long h[2] = {0, 0};
+            hipError_t e = hipMalloc((void**)&d, sizeof h);
+            if (e == hipSuccess) e = hipMemcpy(d, h, sizeof h, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = launch_count(m->plan, d, nullptr);
+            if (e == hipSuccess) e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
+            if (d) (void)hipFree(d);
+            if (e != hipSuccess) return fail(m, PAT_E_DEVICE, std::string("count failed: ") + hipGetErrorString(e));
+            m->work[0] = (double)h[0];
+            m->work[1] = (double)h[1];
+        }
+        *out = c->work[what - 7];
+        return PAT_OK;
+    }
+    default: return PAT_E_ARG;
+    }
+}
+
+}  // extern "C"

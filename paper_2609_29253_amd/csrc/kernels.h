@@ -1,0 +1,37 @@
+// Launch plan handed from the host side to the kernel launchers.  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "patop_internal.h"
+
+namespace patop {
+
+struct ShapeGroup {
+    int shape;              // 0 planar, 1 cylinder
+    const int32_t* kperm;   // device array of transducer indices
+    int nk;
+    int kchunk_fwd, kchunk_adj;
+};
+
+struct LaunchPlan {
+    KParams base;           // geometry, window and table pointers (kperm/nk/kchunk/B per launch)
+    ShapeGroup groups[2];
+    int ngroups;
+    int nbricks;
+    int mode;               // 0 closed form, 1 quadrature
+    bool fp64;
+    int U, L;
+    int jlo, jcnt;          // polyphase filter G[j], j = jlo .. jlo + jcnt - 1
+    const void* G;          // [jcnt] float or double
+    const double* scale;    // [Mcount]
+    double* f;              // [max_batch][K][Mcount] forward workspace
+    void* W;                // [max_batch][K][Mcount] adjoint workspace (float or double)
+    double* z64;            // [max_batch][N] adjoint FP64 partial sums
+};
+
+hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
+hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_t s);
+hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s);
+
+}  // namespace patop

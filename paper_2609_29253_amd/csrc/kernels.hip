@@ -1,0 +1,710 @@
+// Device kernels of the patop library (gfx950).
+//
+// Forward A (Alg. 1):
+//   1. k_fill            f <- 0  (FP64 fine-bin coefficients, [B][K][Mcount])
+//   2. k_fwd_closed /    one work-group per (voxel brick, chunk of transducers):
+//      k_fwd_quad        for each transducer, every voxel of the brick adds
+//                        p0 * |M_i^m| (Alg. 3, Eq. ui_area) or p0 * dA / r into the
+//                        bin of each surface point (Alg. 2, Eq. def_f_point) of an
+//                        LDS FP64 histogram covering the brick's bin window; the
+//                        window is then added to f with FP64 atomics.
+//   3. k_fir             s_hat[l] = sum_j G[j] scale[m] f[m], m = U l - j: the
+//                        convolution with h followed by the block average D_U
+//                        (Eq. discrete_conv, Eq. def_downsampling) as one
+//                        polyphase filter G[j] = 1/U sum_{l'=1..U} h[j + l'];
+//                        scale[m] = U fs dr^2 / (c tau_{m-1/2}) (surface, Eq.
+//                        ui_area) or U fs dr (points).
+// Adjoint A^T (Alg. 5-7):
+//   1. k_adjw            W[m] = scale[m] sum_l G[U l - m] y[l]: transpose of the
+//                        block average and correlation with the reversed kernel.
+//   2. k_adj_closed /    one work-group per (brick, chunk of transducers): W of
+//      k_adj_quad        the brick's bin window is staged in LDS, every voxel
+//                        gathers sum_m |M_i^m| W[m] (FP32 or FP64 per transducer)
+//                        and accumulates over transducers in FP64.
+//   3. k_finish          cast of the FP64 sums when transducer chunks were split
+//                        over work-groups.
+#include <hip/hip_runtime.h>
+
+#include "area.h"
+#include "kernels.h"
+
+namespace patop {
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double* __restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+template <class Real>
+__global__ void k_finish(const double* __restrict__ z, Real* __restrict__ out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (Real)z[i];
+}
+
+__device__ __forceinline__ int floordiv(int a, int b)
+{
+    int q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
+// the voxel owned by this thread and the box of the work-group's brick
+struct Brick {
+    int64_t idx;
+    int ix, iy, iz;
+    bool valid;
+    double lo[3], hi[3];   // axis-aligned box of the brick's voxel centres (global)
+};
+
+__device__ __forceinline__ void brick_setup(const KParams& P, Brick& Bk)
+{
+    const int bid = blockIdx.x;
+    const int bxi = bid % P.nbx, byi = (bid / P.nbx) % P.nby, bzi = bid / (P.nbx * P.nby);
+    const int x0 = bxi * kBrickX, y0 = byi * kBrickY, z0 = bzi * kBrickZ;
+    const int v = threadIdx.x;
+    Bk.ix = x0 + v % kBrickX;
+    Bk.iy = y0 + (v / kBrickX) % kBrickY;
+    Bk.iz = z0 + v / (kBrickX * kBrickY);
+    Bk.valid = Bk.ix < P.n[0] && Bk.iy < P.n[1] && Bk.iz < P.n[2];
+    Bk.idx = Bk.valid ? Bk.ix + P.n[0] * (Bk.iy + P.n[1] * (int64_t)Bk.iz) : 0;
+    const int x1 = (int)min((int64_t)(x0 + kBrickX), P.n[0]) - 1;
+    const int y1 = (int)min((int64_t)(y0 + kBrickY), P.n[1]) - 1;
+    const int z1 = (int)min((int64_t)(z0 + kBrickZ), P.n[2]) - 1;
+    Bk.lo[0] = P.origin[0] + x0 * P.w; Bk.hi[0] = P.origin[0] + x1 * P.w;
+    Bk.lo[1] = P.origin[1] + y0 * P.w; Bk.hi[1] = P.origin[1] + y1 * P.w;
+    Bk.lo[2] = P.origin[2] + z0 * P.w; Bk.hi[2] = P.origin[2] + z1 * P.w;
+}
+
+// bins that any voxel of the brick can reach on transducer T (bounding sphere)
+__device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, const TrDev& T, int& wlo,
+                                             int& whi)
+{
+    double dd = 0.0, dm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double o = fmax(0.0, fmax(Bk.lo[a] - T.cen[a], T.cen[a] - Bk.hi[a]));
+        dd += o * o;
+        double f = fmax(fabs(Bk.lo[a] - T.cen[a]), fabs(Bk.hi[a] - T.cen[a]));
+        dm += f * f;
+    }
+    double dlo = fmax(sqrt(dd) - T.rad, 0.0), dhi = sqrt(dm) + T.rad;
+    int64_t lo = (int64_t)floor(dlo - P.r0);
+    int64_t hi = (int64_t)ceil(dhi - P.r0) + 1;
+    lo = max(lo, P.Mlo);
+    hi = min(hi, P.Mlo + P.Mcount - 1);
+    wlo = (int)lo;
+    whi = (int)hi;
+}
+
+// frame coordinates of a voxel (Sec. 4.1 / Sec. 4.2 frames), FP64
+__device__ __forceinline__ void frame_coords(const TrDev& T, int ix, int iy, int iz, double x[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = fma(T.g[a][0], ix, fma(T.g[a][1], iy, fma(T.g[a][2], iz, T.base[a])));
+}
+
+// ---------------------------------------------------------------------------
+// per-pair geometry: reflected quadrants of the parameter rectangle
+// (Eq. uvminmax; Eq. folded_intervals for the cylinder), built one at a time
+// ---------------------------------------------------------------------------
+
+template <class AT>
+struct PlanarPair {
+    double u[2][2], v[2][2], z2;
+    __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
+    {
+        double L1 = T.p[0], L2 = T.p[1];
+        double u1 = -L1 - x[0], u2 = L1 - x[0], v1 = -L2 - x[1], v2 = L2 - x[1];
+        z2 = x[2] * x[2];
+        u[0][0] = fmax(u1, 0.0); u[0][1] = fmax(u2, 0.0);
+        u[1][0] = fmax(-u2, 0.0); u[1][1] = fmax(-u1, 0.0);
+        v[0][0] = fmax(v1, 0.0); v[0][1] = fmax(v2, 0.0);
+        v[1][0] = fmax(-v2, 0.0); v[1][1] = fmax(-v1, 0.0);
+    }
+    template <class Sink>
+    __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
+    {
+#pragma unroll 1
+        for (int qi = 0; qi < 4; ++qi) {
+            const int i = qi >> 1, j = qi & 1;
+            const double a = i ? u[1][0] : u[0][0], b = i ? u[1][1] : u[0][1];
+            const double c = j ? v[1][0] : v[0][0], d = j ? v[1][1] : v[0][1];
+            if (!(b > a) || !(d > c)) continue;
+            PlQuad<AT> q;
+            pl_setup(q, a, b, c, d, z2, r0);
+            pl_sweep(q, wlo, whi, sink);
+        }
+    }
+};
+
+__device__ __forceinline__ double wrap_pi(double u)
+{
+    if (u <= -M_PI) u += 2.0 * M_PI;
+    if (u <= -M_PI) u += 2.0 * M_PI;
+    if (u > M_PI) u -= 2.0 * M_PI;
+    if (u > M_PI) u -= 2.0 * M_PI;
+    return u;
+}
+
+struct CylinderPair {
+    double u[2][2], v[2][2];
+    int nu;
+    CyPair P;
+    __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
+    {
+        double R = T.p[0], th = T.p[1], Lz = T.p[2];
+        double rho = sqrt64(x[0] * x[0] + x[1] * x[1]);
+        double thi = (rho > 0.0) ? atan2(x[1], x[0]) : 0.0;
+        P.R = R;
+        P.dm = fabs(R - rho);
+        P.mu = 4.0 * R * rho;
+        P.inv_mu = P.mu > 0.0 ? 1.0 / P.mu : 0.0;
+        double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
+        // Eq. folded_intervals
+        if (u1 < 0.0 && 0.0 < u2) { u[0][0] = 0.0; u[0][1] = -u1; u[1][0] = 0.0; u[1][1] = u2; nu = 2; }
+        else if (u2 < u1) { u[0][0] = u1; u[0][1] = M_PI; u[1][0] = -u2; u[1][1] = M_PI; nu = 2; }
+        else if (0.0 <= u1) { u[0][0] = u1; u[0][1] = u2; u[1][0] = u[1][1] = 0.0; nu = 1; }
+        else { u[0][0] = -u2; u[0][1] = -u1; u[1][0] = u[1][1] = 0.0; nu = 1; }
+        double v1 = -Lz - x[2], v2 = Lz - x[2];
+        v[0][0] = fmax(v1, 0.0); v[0][1] = fmax(v2, 0.0);
+        v[1][0] = fmax(-v2, 0.0); v[1][1] = fmax(-v1, 0.0);
+    }
+    template <class Sink>
+    __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
+    {
+#pragma unroll 1
+        for (int qi = 0; qi < 4; ++qi) {
+            const int i = qi >> 1, j = qi & 1;
+            if (i >= nu) break;
+            const double a = i ? u[1][0] : u[0][0], b = i ? u[1][1] : u[0][1];
+            const double c = j ? v[1][0] : v[0][0], d = j ? v[1][1] : v[0][1];
+            if (!(b > a) || !(d > c)) continue;
+            CyQuad q;
+            cy_setup(q, P, a, b, c, d, r0);
+            cy_sweep(q, P, r0, wlo, whi, sink);
+        }
+    }
+};
+
+template <int SHAPE, class AT> struct PairOf;
+template <class AT> struct PairOf<0, AT> { using type = PlanarPair<AT>; };
+template <class AT> struct PairOf<1, AT> { using type = CylinderPair; };
+
+// ---------------------------------------------------------------------------
+// forward, closed-form areas
+// ---------------------------------------------------------------------------
+
+template <int SHAPE, class AT, int NB, class Real>
+__global__ __launch_bounds__(kThreads) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
+                                                          double* __restrict__ f)
+{
+    extern __shared__ double hist[];   // [NB][kHist]
+    Brick Bk;
+    brick_setup(P, Bk);
+    double p0[NB];
+    bool nz = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        p0[b] = Bk.valid ? (double)coef[b * P.N + Bk.idx] : 0.0;
+        nz |= p0[b] != 0.0;
+    }
+    if (!__syncthreads_or(nz)) return;
+    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    for (int kk = kbeg; kk < kend; ++kk) {
+        const int k = P.kperm[kk];
+        const TrDev T = P.tr[k];
+        int wlo, whi;
+        brick_window(P, Bk, T, wlo, whi);
+        for (int plo = wlo; plo <= whi; plo += kHist) {
+            const int phi = min(whi, plo + kHist - 1);
+            const int wn = phi - plo + 1;
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) hist[b * kHist + i] = 0.0;
+            __syncthreads();
+            if (nz) {
+                double x[3];
+                frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+                typename PairOf<SHAPE, AT>::type pair;
+                pair.setup(T, x, P.r0);
+                auto sink = [&](int m, auto area) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (m - plo)], p0[b] * (double)area);
+                };
+                pair.sweep(plo, phi, sink, P.r0);
+            }
+            __syncthreads();
+            const int64_t fo = (plo - P.Mlo);
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    double v = hist[b * kHist + i];
+                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + fo + i], v);
+                }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, closed-form areas
+// ---------------------------------------------------------------------------
+
+template <int SHAPE, class AT, int NB, class Real>
+__global__ __launch_bounds__(kThreads) void k_adj_closed(KParams P, const Real* __restrict__ W,
+                                                          Real* __restrict__ out, double* __restrict__ z64,
+                                                          int direct)
+{
+    extern __shared__ double smem_d[];
+    Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][kHist]
+    Brick Bk;
+    brick_setup(P, Bk);
+    double acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    for (int kk = kbeg; kk < kend; ++kk) {
+        const int k = P.kperm[kk];
+        const TrDev T = P.tr[k];
+        int wlo, whi;
+        brick_window(P, Bk, T, wlo, whi);
+        for (int plo = wlo; plo <= whi; plo += kHist) {
+            const int phi = min(whi, plo + kHist - 1);
+            const int wn = phi - plo + 1;
+            __syncthreads();
+            const int64_t fo = (plo - P.Mlo);
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) Ws[b * kHist + i] = W[((int64_t)b * P.K + k) * P.Mcount + fo + i];
+            __syncthreads();
+            if (Bk.valid) {
+                double x[3];
+                frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+                typename PairOf<SHAPE, AT>::type pair;
+                pair.setup(T, x, P.r0);
+                AT part[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) part[b] = AT(0);
+                auto sink = [&](int m, auto area) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) part[b] = fma((AT)area, (AT)Ws[b * kHist + (m - plo)], part[b]);
+                };
+                pair.sweep(plo, phi, sink, P.r0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[b] += (double)part[b];
+            }
+        }
+    }
+    if (!Bk.valid) return;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (direct) out[b * P.N + Bk.idx] = (Real)acc[b];
+        else unsafeAtomicAdd(&z64[b * P.N + Bk.idx], acc[b]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// quadrature over surface points (Alg. 2 / Alg. 6)
+// ---------------------------------------------------------------------------
+
+// bin of the distance sqrt(r2): [r0 + m - 1, r0 + m); FP32 estimate, FP64 decision
+__device__ __forceinline__ int point_bin(double r2, double r0, float r0f)
+{
+    float rf = __builtin_sqrtf((float)r2);
+    int m = (int)floorf(rf - r0f) + 1;
+    double e = r0 + (double)(m - 1);
+    if (r2 < e * e) return m - 1;
+    e += 1.0;
+    if (!(r2 < e * e)) return m + 1;
+    return m;
+}
+
+template <class AT> __device__ __forceinline__ AT inv_dist(double r2);
+template <> __device__ __forceinline__ float inv_dist<float>(double r2) { return __builtin_amdgcn_rsqf((float)r2); }
+template <> __device__ __forceinline__ double inv_dist<double>(double r2) { return rsq64(r2); }
+
+template <class AT, int NB, class Real>
+__global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __restrict__ coef,
+                                                        double* __restrict__ f)
+{
+    extern __shared__ double hist[];
+    Brick Bk;
+    brick_setup(P, Bk);
+    double p0[NB];
+    bool nz = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        p0[b] = Bk.valid ? (double)coef[b * P.N + Bk.idx] : 0.0;
+        nz |= p0[b] != 0.0;
+    }
+    const double X0 = P.origin[0] + Bk.ix * P.w, X1 = P.origin[1] + Bk.iy * P.w, X2 = P.origin[2] + Bk.iz * P.w;
+    if (!__syncthreads_or(nz)) return;
+    const float r0f = (float)P.r0;
+    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    for (int kk = kbeg; kk < kend; ++kk) {
+        const int k = P.kperm[kk];
+        const TrDev T = P.tr[k];
+        const double* __restrict__ Q = P.qpts + (int64_t)k * P.Q * 3;
+        const AT dA = (AT)P.qdA[k];
+        int wlo, whi;
+        brick_window(P, Bk, T, wlo, whi);
+        for (int plo = wlo; plo <= whi; plo += kHist) {
+            const int phi = min(whi, plo + kHist - 1);
+            const int wn = phi - plo + 1;
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) hist[b * kHist + i] = 0.0;
+            __syncthreads();
+            if (nz) {
+                int mcur = -(1 << 30);
+                AT acc = AT(0);
+                for (int q = 0; q < P.Q; ++q) {
+                    double dx = Q[3 * q] - X0, dy = Q[3 * q + 1] - X1, dz = Q[3 * q + 2] - X2;
+                    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    int m = point_bin(r2, P.r0, r0f);
+                    AT cv = dA * inv_dist<AT>(r2);
+                    if (m != mcur) {
+                        if (mcur >= plo && mcur <= phi)
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (mcur - plo)], p0[b] * (double)acc);
+                        mcur = m;
+                        acc = cv;
+                    } else {
+                        acc += cv;
+                    }
+                }
+                if (mcur >= plo && mcur <= phi)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (mcur - plo)], p0[b] * (double)acc);
+            }
+            __syncthreads();
+            const int64_t fo = (plo - P.Mlo);
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    double v = hist[b * kHist + i];
+                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + fo + i], v);
+                }
+            __syncthreads();
+        }
+    }
+}
+
+template <class AT, int NB, class Real>
+__global__ __launch_bounds__(kThreads) void k_adj_quad(KParams P, const Real* __restrict__ W,
+                                                        Real* __restrict__ out, double* __restrict__ z64,
+                                                        int direct)
+{
+    extern __shared__ double smem_d[];
+    Real* Ws = reinterpret_cast<Real*>(smem_d);
+    Brick Bk;
+    brick_setup(P, Bk);
+    double acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+    const double X0 = P.origin[0] + Bk.ix * P.w, X1 = P.origin[1] + Bk.iy * P.w, X2 = P.origin[2] + Bk.iz * P.w;
+    const float r0f = (float)P.r0;
+    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    for (int kk = kbeg; kk < kend; ++kk) {
+        const int k = P.kperm[kk];
+        const TrDev T = P.tr[k];
+        const double* __restrict__ Q = P.qpts + (int64_t)k * P.Q * 3;
+        const AT dA = (AT)P.qdA[k];
+        int wlo, whi;
+        brick_window(P, Bk, T, wlo, whi);
+        for (int plo = wlo; plo <= whi; plo += kHist) {
+            const int phi = min(whi, plo + kHist - 1);
+            const int wn = phi - plo + 1;
+            __syncthreads();
+            const int64_t fo = (plo - P.Mlo);
+            for (int i = threadIdx.x; i < wn; i += kThreads)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) Ws[b * kHist + i] = W[((int64_t)b * P.K + k) * P.Mcount + fo + i];
+            __syncthreads();
+            if (Bk.valid) {
+                AT part[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) part[b] = AT(0);
+                for (int q = 0; q < P.Q; ++q) {
+                    double dx = Q[3 * q] - X0, dy = Q[3 * q + 1] - X1, dz = Q[3 * q + 2] - X2;
+                    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    int m = point_bin(r2, P.r0, r0f);
+                    if (m < plo || m > phi) continue;
+                    AT cv = dA * inv_dist<AT>(r2);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) part[b] = fma(cv, (AT)Ws[b * kHist + (m - plo)], part[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[b] += (double)part[b];
+            }
+        }
+    }
+    if (!Bk.valid) return;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (direct) out[b * P.N + Bk.idx] = (Real)acc[b];
+        else unsafeAtomicAdd(&z64[b * P.N + Bk.idx], acc[b]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// work count: area evaluations (closed form: one per quadrant and bin inside the
+// kept range; quadrature: one per surface point) and voxel-transducer pairs
+// ---------------------------------------------------------------------------
+
+template <int SHAPE>
+__global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigned long long* __restrict__ out)
+{
+    __shared__ unsigned long long red[2];
+    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    __syncthreads();
+    Brick Bk;
+    brick_setup(P, Bk);
+    unsigned long long evals = 0, pairs = 0;
+    if (Bk.valid) {
+        for (int kk = 0; kk < P.nk; ++kk) {
+            const TrDev T = P.tr[P.kperm[kk]];
+            if (quad) { evals += P.Q; pairs += 1; continue; }
+            double x[3];
+            frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+            const int lo = (int)P.Mlo, hi = (int)(P.Mlo + P.Mcount - 1);
+            int nb = 0;
+            auto sink = [&](int, auto) { ++nb; };
+            typename PairOf<SHAPE, double>::type pair;
+            pair.setup(T, x, P.r0);
+            pair.sweep(lo, hi, sink, P.r0);
+            evals += nb;
+            pairs += 1;
+        }
+    }
+    atomicAdd(&red[0], evals);
+    atomicAdd(&red[1], pairs);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], red[0]);
+        atomicAdd(&out[1], red[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// temporal stage
+// ---------------------------------------------------------------------------
+
+// s_hat[b][k][l] = sum_j G[j] scale[m] f[b][k][m],  m = U l - (jlo + jj)  (0-based l)
+template <class Real>
+__global__ void k_fir(const double* __restrict__ f, const double* __restrict__ scale, const Real* __restrict__ G,
+                      int jlo, int jcnt, int U, int L, int K, int64_t Mlo, int64_t Mcount, Real* __restrict__ out)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y, b = blockIdx.z;
+    if (l >= L) return;
+    const double* fk = f + ((int64_t)b * K + k) * Mcount;
+    Real acc = Real(0);
+    const int64_t mtop = (int64_t)U * l - jlo;   // m for jj = 0
+    for (int jj = 0; jj < jcnt; ++jj) {
+        int64_t mi = mtop - jj - Mlo;
+        if (mi < 0 || mi >= Mcount) continue;
+        acc = fma(G[jj], (Real)(scale[mi] * fk[mi]), acc);
+    }
+    out[((int64_t)b * K + k) * L + l] = acc;
+}
+
+// W[b][k][m] = scale[m] sum_l G[U l - m] y[b][k][l]
+template <class Real>
+__global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ scale, const Real* __restrict__ G,
+                       int jlo, int jcnt, int U, int L, int K, int64_t Mlo, int64_t Mcount, Real* __restrict__ W)
+{
+    const int64_t mi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int k = blockIdx.y, b = blockIdx.z;
+    if (mi >= Mcount) return;
+    const int m = (int)(Mlo + mi);
+    const Real* yk = y + ((int64_t)b * K + k) * L;
+    // U l - m = j in [jlo, jlo + jcnt - 1]
+    int lmin = -floordiv(-(m + jlo), U);
+    int lmax = floordiv(m + jlo + jcnt - 1, U);
+    lmin = max(lmin, 0);
+    lmax = min(lmax, L - 1);
+    Real acc = Real(0);
+    for (int l = lmin; l <= lmax; ++l) acc = fma(G[U * l - m - jlo], yk[l], acc);
+    W[((int64_t)b * K + k) * Mcount + mi] = (Real)scale[mi] * acc;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <int SHAPE, class AT, class Real>
+hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
+{
+    size_t sh = (size_t)nb * kHist * sizeof(double);
+    switch (nb) {
+    case 1: k_fwd_closed<SHAPE, AT, 1, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 2: k_fwd_closed<SHAPE, AT, 2, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 4: k_fwd_closed<SHAPE, AT, 4, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    default: k_fwd_closed<SHAPE, AT, 8, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <int SHAPE, class AT, class Real>
+hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
+                         hipStream_t s)
+{
+    size_t sh = (size_t)nb * kHist * sizeof(Real);
+    switch (nb) {
+    case 1: k_adj_closed<SHAPE, AT, 1, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_closed<SHAPE, AT, 2, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_closed<SHAPE, AT, 4, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_closed<SHAPE, AT, 8, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    }
+    return hipGetLastError();
+}
+
+template <class AT, class Real>
+hipError_t fwd_quad_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
+{
+    size_t sh = (size_t)nb * kHist * sizeof(double);
+    switch (nb) {
+    case 1: k_fwd_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 2: k_fwd_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 4: k_fwd_quad<AT, 4, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    default: k_fwd_quad<AT, 8, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <class AT, class Real>
+hipError_t adj_quad_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
+                       hipStream_t s)
+{
+    size_t sh = (size_t)nb * kHist * sizeof(Real);
+    switch (nb) {
+    case 1: k_adj_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_quad<AT, 4, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_quad<AT, 8, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    }
+    return hipGetLastError();
+}
+
+int chunk_nb(int rem)
+{
+    return rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+}
+
+int grid_fill_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+template <class Real>
+hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hipStream_t s)
+{
+    hipError_t e;
+    const int64_t nf = (int64_t)B * L.base.K * L.base.Mcount;
+    k_fill<<<grid_fill_blocks(nf), 256, 0, s>>>(L.f, nf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int b0 = 0; b0 < B;) {
+        const int nb = chunk_nb(B - b0);
+        for (int g = 0; g < L.ngroups; ++g) {
+            const ShapeGroup& G = L.groups[g];
+            KParams P = L.base;
+            P.kperm = G.kperm;
+            P.nk = G.nk;
+            P.kchunk = G.kchunk_fwd;
+            P.B = nb;
+            dim3 grid(L.nbricks, (G.nk + G.kchunk_fwd - 1) / G.kchunk_fwd);
+            const Real* cb = coef + (int64_t)b0 * P.N;
+            double* fb = L.f + (int64_t)b0 * P.K * P.Mcount;
+            if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
+            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real>(nb, grid, P, cb, fb, s);
+            else e = fwd_closed_nb<1, double, Real>(nb, grid, P, cb, fb, s);
+            if (e != hipSuccess) return e;
+        }
+        b0 += nb;
+    }
+    dim3 g2((L.L + 255) / 256, L.base.K, B);
+    k_fir<Real><<<g2, 256, 0, s>>>(L.f, L.scale, (const Real*)L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
+                                   L.base.Mlo, L.base.Mcount, sig);
+    return hipGetLastError();
+}
+
+template <class Real>
+hipError_t adjoint_t(const LaunchPlan& L, const Real* sig, Real* coef, int B, hipStream_t s)
+{
+    hipError_t e;
+    Real* W = (Real*)L.W;
+    dim3 g1((unsigned)((L.base.Mcount + 255) / 256), L.base.K, B);
+    k_adjw<Real><<<g1, 256, 0, s>>>(sig, L.scale, (const Real*)L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
+                                    L.base.Mlo, L.base.Mcount, W);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bool direct = L.ngroups == 1 && L.groups[0].kchunk_adj >= L.groups[0].nk;
+    const int64_t nz = (int64_t)B * L.base.N;
+    if (!direct) {
+        k_fill<<<grid_fill_blocks(nz), 256, 0, s>>>(L.z64, nz);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int b0 = 0; b0 < B;) {
+        const int nb = chunk_nb(B - b0);
+        for (int g = 0; g < L.ngroups; ++g) {
+            const ShapeGroup& G = L.groups[g];
+            KParams P = L.base;
+            P.kperm = G.kperm;
+            P.nk = G.nk;
+            P.kchunk = G.kchunk_adj;
+            P.B = nb;
+            dim3 grid(L.nbricks, (G.nk + G.kchunk_adj - 1) / G.kchunk_adj);
+            const Real* Wb = W + (int64_t)b0 * P.K * P.Mcount;
+            Real* ob = coef + (int64_t)b0 * P.N;
+            double* zb = L.z64 + (int64_t)b0 * P.N;
+            if (L.mode == 1) e = adj_quad_nb<Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
+            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
+            else e = adj_closed_nb<1, double, Real>(nb, grid, P, Wb, ob, zb, direct, s);
+            if (e != hipSuccess) return e;
+        }
+        b0 += nb;
+    }
+    if (!direct) {
+        k_finish<Real><<<grid_fill_blocks(nz), 256, 0, s>>>(L.z64, coef, nz);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_t s)
+{
+    for (int g = 0; g < L.ngroups; ++g) {
+        KParams P = L.base;
+        P.kperm = L.groups[g].kperm;
+        P.nk = L.groups[g].nk;
+        if (L.groups[g].shape == 0) k_count<0><<<L.nbricks, kThreads, 0, s>>>(P, L.mode, out);
+        else k_count<1><<<L.nbricks, kThreads, 0, s>>>(P, L.mode, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s)
+{
+    if (L.fp64) return forward_t<double>(L, (const double*)coef, (double*)sig, B, s);
+    return forward_t<float>(L, (const float*)coef, (float*)sig, B, s);
+}
+
+hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s)
+{
+    if (L.fp64) return adjoint_t<double>(L, (const double*)sig, (double*)coef, B, s);
+    return adjoint_t<float>(L, (const float*)sig, (float*)coef, B, s);
+}
+
+}  // namespace patop

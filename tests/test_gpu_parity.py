@@ -1,0 +1,81 @@
+"""HIP path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (relative L2 over the whole output):
+  FP32 variant: 1e-5 (the target accuracy of the FP32 operator);
+  FP64 variant: 1e-11 (two independent FP64 evaluations of the same areas; the
+  planar and elliptic closed forms each carry ~1e-13 relative rounding per bin
+  from differences of nearby edge quantities).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import pat_inputs as P
+from conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-11}
+DT = {"fp32": torch.float32, "fp64": torch.float64}
+
+
+def run_gpu(prob, mode, prec, coef=None, y=None):
+    from paper_2609_29253_amd.operator import PatOperator
+    coef = prob.coef if coef is None else coef
+    y = prob.y if y is None else y
+    B = max(coef.shape[0], y.shape[0])
+    op = PatOperator.from_problem(prob, mode=mode, precision=prec, max_batch=B)
+    dev = torch.device("cuda", 0)
+    s = op.forward(torch.tensor(coef, dtype=DT[prec], device=dev))
+    z = op.adjoint(torch.tensor(y, dtype=DT[prec], device=dev))
+    torch.cuda.synchronize()
+    out = s.double().cpu().numpy(), z.double().cpu().numpy()
+    op.close()
+    return out
+
+
+SMALL = [
+    # shape, U, B, n, K, L
+    (P.PLANAR, 1, 1, 13, 5, 200),
+    (P.PLANAR, 3, 2, 9, 4, 200),
+    (P.CYLINDER, 1, 1, 13, 5, 260),
+    (P.CYLINDER, 2, 3, 9, 4, 260),
+]
+
+
+@pytest.mark.parametrize("mode", ["closed", "quadrature"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{'pl' if c[0] == 0 else 'cy'}_U{c[1]}_B{c[2]}_n{c[3]}")
+def test_small_parity(gpu, case, prec, mode):
+    shape, U, B, n, K, L = case
+    p = P.small_case(shape, n=n, K=K, U=U, B=B, L=L, seed=3)
+    p.quad_n = (6, 5)
+    omode = O.MODE_SURFACE if mode == "closed" else O.MODE_POINT
+    print(f"case {p.name} U={U} B={B} {prec} {mode}", flush=True)
+    s_ref = O.forward(p, mode=omode)
+    z_ref = O.adjoint(p, mode=omode)
+    s, z = run_gpu(p, mode, prec)
+    es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
+    print(f"  forward rel L2 {es:.3e}  adjoint rel L2 {ez:.3e}", flush=True)
+    assert es < TOL[prec] and ez < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_config1_full(gpu, prec):
+    """Planar 64 x 32^3, every output against the oracle, plus the dot test."""
+    p = P.config1()
+    s_ref = O.forward(p)
+    z_ref = O.adjoint(p)
+    s, z = run_gpu(p, "closed", prec)
+    es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
+    lhs, rhs = float(np.sum(s * p.y)), float(np.sum(z * p.coef))
+    print(f"cfg1 {prec}: forward {es:.3e} adjoint {ez:.3e} dot gap {abs(lhs - rhs) / abs(lhs):.3e}", flush=True)
+    assert es < TOL[prec] and ez < TOL[prec]
+    assert abs(lhs - rhs) / abs(lhs) < (1e-5 if prec == "fp32" else 1e-11)
+
+
+def test_zero_input_gives_zero(gpu):
+    p = P.small_case(P.CYLINDER, n=9, K=3, L=260)
+    s, z = run_gpu(p, "closed", "fp32", coef=np.zeros_like(p.coef), y=np.zeros_like(p.y))
+    assert not np.any(s) and not np.any(z)
