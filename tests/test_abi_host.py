@@ -1,0 +1,107 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+and its host-only logic (system-kernel builder, geometry validation) behaves.
+No GPU compute is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pat_inputs as P
+from conftest import ROOT, rel_l2
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "patop.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pat_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_29253_amd import _lib
+    L = _lib.lib()
+    names = declared_symbols()
+    assert "pat_forward" in names and "pat_adjoint" in names and "pat_set_geometry" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_status_strings():
+    from paper_2609_29253_amd import _lib
+    L = _lib.lib()
+    assert L.pat_status_string(0) == b"ok"
+    assert b"geometry not set" == L.pat_status_string(6)
+    assert L.pat_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("U", [1, 2, 5])
+@pytest.mark.parametrize("phi", [P.PHI_CONE, P.PHI_WENDLAND2])
+def test_kernel_builder_matches_oracle(U, phi):
+    """Two independent quadratures of Eq. def_bh agree to rounding."""
+    from paper_2609_29253_amd.operator import build_kernel
+    eir = P.Eir.gauss_cos()
+    h, nf = build_kernel(phi, 0.15e-3, eir, 1500.0, 50e6, U)
+    ho, nfo = O.build_kernel(phi, 0.15e-3, eir, 1500.0, 50e6, U)
+    assert nf == nfo and len(h) == len(ho)
+    assert np.max(np.abs(h - ho)) < 1e-13 * np.max(np.abs(ho))
+
+
+def test_kernel_builder_sampled_eir():
+    from paper_2609_29253_amd.operator import build_kernel
+    t = np.arange(0, 40) * 25e-9
+    e = P.Eir(P.EIR_SAMPLED, samples=np.sin(2 * np.pi * 5e6 * t) * np.exp(-((t - 0.5e-6) / 0.2e-6) ** 2), dt=25e-9)
+    h, nf = build_kernel(P.PHI_WENDLAND2, 0.15e-3, e, 1500.0, 40e6, 2)
+    ho, nfo = O.build_kernel(P.PHI_WENDLAND2, 0.15e-3, e, 1500.0, 40e6, 2)
+    assert nf == nfo and rel_l2(h, ho) < 1e-12
+    assert abs(h.sum()) < 1e-12 * np.abs(h).sum()
+
+
+def test_kernel_builder_rejects_bad_arguments():
+    from paper_2609_29253_amd import _lib
+    from paper_2609_29253_amd.operator import build_kernel
+    with pytest.raises(_lib.PatError):
+        build_kernel(7, 0.15e-3, P.Eir.gauss_cos(), 1500.0, 50e6, 1)
+    with pytest.raises(_lib.PatError):
+        build_kernel(P.PHI_CONE, -1.0, P.Eir.gauss_cos(), 1500.0, 50e6, 1)
+
+
+def test_geometry_validation():
+    from paper_2609_29253_amd import _lib
+    from paper_2609_29253_amd.operator import check_geometry
+    p = P.config1()
+    g = (p.grid.n, p.grid.origin, p.grid.spacing)
+    d = check_geometry(p.tr.packed, *g, p.kappa)
+    assert 15e-3 < d < 20e-3
+    bad = p.tr.packed.copy()
+    bad[0, 4:7] *= 1.01                        # e1 not unit
+    with pytest.raises(_lib.PatError) as e:
+        check_geometry(bad, *g, p.kappa)
+    assert e.value.status == 2
+    bad = p.tr.packed.copy()
+    bad[3, 10] = 0.0                           # zero width
+    with pytest.raises(_lib.PatError) as e:
+        check_geometry(bad, *g, p.kappa)
+    assert e.value.status == 3
+    bad = p.tr.packed.copy()
+    bad[5, 1:4] = [0.0, 0.0, 1.0e-3]           # inside the grid
+    with pytest.raises(_lib.PatError) as e:
+        check_geometry(bad, *g, p.kappa)
+    assert e.value.status == 4
+    cyl = P.config4_fd().tr.packed.copy()
+    cyl[0, 13] = math.pi / 2                   # theta_max must be < pi/2
+    with pytest.raises(_lib.PatError) as e:
+        check_geometry(cyl, (10, 10, 10), (-0.45e-3,) * 3, 0.1e-3, 0.15e-3)
+    assert e.value.status == 3
+
+
+def test_forward_without_geometry_is_a_state_error():
+    """A context that never received a geometry refuses to run (host check only)."""
+    from paper_2609_29253_amd import _lib
+    L = _lib.lib()
+    out = ctypes.c_double(0)
+    assert L.pat_query(None, 6, ctypes.byref(out)) == 0 and out.value == 1
+    assert L.pat_forward(None, None, None, 1, None) == 1
