@@ -552,6 +552,8 @@ void or_quad_points(const double* tr, int n1, int n2, double* pts, double* dA)
     }
 }
 
+int or_num_threads(void);
+
 /* ------------------------------------------------------------------------- */
 /* Operator                                                                   */
 /* ------------------------------------------------------------------------- */
@@ -590,12 +592,12 @@ static void voxel_xyz(const oop* o, long i, double* x)
 }
 
 /* geometric coefficients f_k on bins [Mlo, Mhi] (Alg. 3 or Alg. 2), B volumes */
-static void fcoef(const oop* o, int k, const double* coef, int B, long N, double* f /* B x M */)
+static void fcoef_range(const oop* o, int k, const double* coef, int B, long N, long i0, long i1,
+                        double* f /* B x M, accumulated */)
 {
     long M = o->Mhi - o->Mlo + 1;
     const double* tr = o->tr + 16 * (long)k;
     double ufs = o->U * o->fs;
-    memset(f, 0, sizeof(double) * M * B);
     double* tmp = NULL;
     long cap = 1 << 16;
     double *pts = NULL, dA = 0.0;
@@ -605,7 +607,7 @@ static void fcoef(const oop* o, int k, const double* coef, int B, long N, double
         pts = (double*)malloc(sizeof(double) * 3 * Q);
         or_quad_points(tr, o->q1, o->q2, pts, &dA);
     }
-    for (long i = 0; i < N; ++i) {
+    for (long i = i0; i < i1; ++i) {
         int any = 0;
         for (int b = 0; b < B; ++b) any |= coef[b * N + i] != 0.0;
         if (!any) continue;
@@ -632,9 +634,38 @@ static void fcoef(const oop* o, int k, const double* coef, int B, long N, double
             }
         }
     }
-    for (long j = 0; j < M * B; ++j) f[j] *= ufs;
     free(tmp);
     free(pts);
+}
+
+/* geometric coefficients f_k on bins [Mlo, Mhi] (Alg. 3 or Alg. 2), B volumes;
+   when `par` is set the voxel loop is shared by the OpenMP threads (each keeps
+   its own partial f, summed at the end) */
+static void fcoef(const oop* o, int k, const double* coef, int B, long N, double* f, int par)
+{
+    long M = o->Mhi - o->Mlo + 1;
+    double ufs = o->U * o->fs;
+    memset(f, 0, sizeof(double) * M * B);
+    if (!par) {
+        fcoef_range(o, k, coef, B, N, 0, N, f);
+    } else {
+#pragma omp parallel
+        {
+            double* loc = (double*)calloc((size_t)M * B, sizeof(double));
+            int nt = 1, id = 0;
+#ifdef _OPENMP
+            nt = omp_get_num_threads();
+            id = omp_get_thread_num();
+#endif
+            long chunk = (N + nt - 1) / nt;
+            long a = id * chunk, b = a + chunk < N ? a + chunk : N;
+            if (a < b) fcoef_range(o, k, coef, B, N, a, b, loc);
+#pragma omp critical
+            for (long j = 0; j < M * B; ++j) f[j] += loc[j];
+            free(loc);
+        }
+    }
+    for (long j = 0; j < M * B; ++j) f[j] *= ufs;
 }
 
 /* s_hat[l] = 1/U sum_{l'=1..U} (h * f)[U(l-1) + l'], l = 1..L (Eq. discrete_conv) */
@@ -666,7 +697,7 @@ void or_fcoef(const double* tr, int K, const long* n, const double* origin, doub
     op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2);
     *Mlo = o.Mlo;
     *Mhi = o.Mhi;
-    if (f) fcoef(&o, k, coef, B, n[0] * n[1] * n[2], f);
+    if (f) fcoef(&o, k, coef, B, n[0] * n[1] * n[2], f, 0);
 }
 
 /* Forward operator on a subset of transducers (Alg. 1).  out is B x nk x L. */
@@ -679,11 +710,20 @@ void or_forward(const double* tr, int K, const long* n, const double* origin, do
     op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2);
     long N = n[0] * n[1] * n[2];
     long M = o.Mhi - o.Mlo + 1;
+    if (nk >= or_num_threads()) {
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int kk = 0; kk < nk; ++kk) {
+        for (int kk = 0; kk < nk; ++kk) {
+            double* f = (double*)malloc(sizeof(double) * M * B);
+            fcoef(&o, ksub[kk], coef, B, N, f, 0);
+            for (int b = 0; b < B; ++b) conv_down(&o, f + b * M, out + ((long)b * nk + kk) * L);
+            free(f);
+        }
+    } else {
         double* f = (double*)malloc(sizeof(double) * M * B);
-        fcoef(&o, ksub[kk], coef, B, N, f);
-        for (int b = 0; b < B; ++b) conv_down(&o, f + b * M, out + ((long)b * nk + kk) * L);
+        for (int kk = 0; kk < nk; ++kk) {
+            fcoef(&o, ksub[kk], coef, B, N, f, 1);
+            for (int b = 0; b < B; ++b) conv_down(&o, f + b * M, out + ((long)b * nk + kk) * L);
+        }
         free(f);
     }
 }

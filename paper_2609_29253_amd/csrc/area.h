@@ -68,7 +68,20 @@ __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsq64(
 
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt64(x); }
-__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+// atan2 for y, x >= 0.  Small angles (y <= x/5) take the odd Taylor series of
+// atan(y/x), whose error is the rounding of a few correctly rounded operations;
+// the library routine's error, a smooth function of its argument, would be
+// shared by neighbouring voxels and survive their summation into one bin.
+__device__ __forceinline__ float atan2_t(float y, float x)
+{
+    if (y <= 0.2f * x) {
+        float t = y / x, u = t * t;
+        float p = fmaf(u, fmaf(u, fmaf(u, fmaf(u, fmaf(u, fmaf(u, 1.0f / 13, -1.0f / 11), 1.0f / 9), -1.0f / 7),
+                                       1.0f / 5), -1.0f / 3), 1.0f);
+        return t * p;
+    }
+    return atan2f(y, x);
+}
 __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float atan_t(float x) { return atanf(x); }
 __device__ __forceinline__ double atan_t(double x) { return atan(x); }
@@ -89,7 +102,7 @@ template <> struct AtanMx<float> {
     {
         if (x > 4.0f) return atanf(x) - x;
         float acc = 0.0f, scale = 1.0f;
-        for (int i = 0; i < 3 && x >= 0.2f; ++i) {
+        for (int i = 0; i < 4 && x >= 0.1f; ++i) {
             float q = 1.0f + __builtin_sqrtf(fmaf(x, x, 1.0f));
             float iq = 1.0f / q;
             acc = fmaf(-scale * x * x * x, iq * iq, acc);
@@ -97,7 +110,8 @@ template <> struct AtanMx<float> {
             scale *= 2.0f;
         }
         float y = x * x;
-        float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, 1.0f / 11, -1.0f / 9), 1.0f / 7), -1.0f / 5), 1.0f / 3);
+        float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, -1.0f / 13, 1.0f / 11), -1.0f / 9), 1.0f / 7), -1.0f / 5),
+                       1.0f / 3);
         return fmaf(-scale * x * y, p, acc);
     }
 };
@@ -195,7 +209,7 @@ enum { KEDGE = 0, KAC = 1, KAD = 2, KBC = 3, KBD = 4 };
 // Walk the bins [max(mfirst, wlo), min(mlast, whi)] of a planar quadrant; sink(m, area)
 // receives the area in dr^2 units.
 template <class T, class Sink>
-__device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, Sink& sink)
+__device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
@@ -283,7 +297,7 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, S
         if (next == KAD) { hiS = true; wh0 = q.a; }
         if (next == KBC) { loA = true; wl0 = q.c; }
         if (next == KEDGE || next == KBD) {
-            sink(m, T(0.5) * acc);
+            sink(m, T(0.5) * wgt * acc);
             acc = T(0);
             if (next == KBD || m >= me) break;
             ++m;
@@ -296,7 +310,7 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, S
 // ---------------------------------------------------------------------------
 
 struct CyPair {
-    double R, dm, mu, inv_mu;    // radius, |R - rho|, 4 R rho, 1/mu (0 when rho = 0)
+    double R, dm, mu, isq_mu;    // radius, |R - rho|, 4 R rho, 1/sqrt(mu) (0 when rho = 0)
 };
 
 struct CyQuad {
@@ -335,30 +349,31 @@ __device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, d
     q.mlast = (int)ceil(q.Dbd - r0);
 }
 
-// one end point of the level curve on the line v (Eq. alphabeta), half-angle form
+// one end point of the level curve on the line v (Eq. alphabeta), half-angle form;
+// isK = 1/sqrt(r^2 - (R - rho)^2)
 __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, double r, double v,
-                                            double Dav, double Dbv, double iK, double& s, double& c,
+                                            double Dav, double Dbv, double isK, double& s, double& c,
                                             double& dl)
 {
     double qa = (r - Dav) * (r + Dav);          // r^2 - v^2 - psi(a)
     if (!(qa > 0.0)) {
         s = q.sa; c = q.ca;
-        dl = sqrt64((r - q.Da0) * (r + q.Da0) * iK);
+        dl = sqrt64((r - q.Da0) * (r + q.Da0)) * isK;
         return;
     }
     double qb = (r - Dbv) * (r + Dbv);          // r^2 - v^2 - psi(b)
     if (!(qb < 0.0)) {
         s = q.sb; c = q.cb;
-        dl = sqrt64((r - q.Db0) * (r + q.Db0) * iK);
+        dl = sqrt64((r - q.Db0) * (r + q.Db0)) * isK;
         return;
     }
-    s = sqrt64((qa + q.musa2) * P.inv_mu);
-    c = sqrt64((q.mucb2 - qb) * P.inv_mu);
-    dl = v * sqrt64(iK);
+    s = sqrt64(qa + q.musa2) * P.isq_mu;
+    c = sqrt64(q.mucb2 - qb) * P.isq_mu;
+    dl = v * isK;
 }
 
 // E(sigma, nu) from sin, cos and Delta of sigma (Carlson's duplication with the
-// stopping rule of Carlson 1995, tolerance 1e-13; DLMF 19.36.1-2)
+// stopping rule of Carlson 1995 for a relative tolerance of 1e-13; DLMF 19.36.1-2)
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu)
 {
     double x = c * c, y = dl * dl, z = 1.0;
@@ -369,6 +384,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
     const double Qf = 125.0;   // (3 * 1e-13)^(-1/6)
     double p4 = 1.0, sumD = 0.0;
+#pragma unroll 1
     for (int it = 0; it < 12 && p4 * Qf * dev >= fmin(AF, AD); ++it) {
         double lam = fma(sx, sy, fma(sx, sz, sy * sz));
         sumD = fma(p4, rcp64(sz * (z + lam)), sumD);
@@ -382,12 +398,11 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
         sy = sqrt64(y);
         sz = sqrt64(z);
     }
-    double iAF = rcp64(AF);
+    double rAF = rsq64(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
-    double rf = (1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0)) *
-                rsq64(AF);
-    double iAD = rcp64(AD);
+    double rf = (1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0)) * rAF;
+    double rAD = rsq64(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
     Y = (AD - y) * iAD;
     Z = -(X + Y) * (1.0 / 3.0);
@@ -395,7 +410,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double D2 = XY - 6.0 * Z2, D3 = (3.0 * XY - 8.0 * Z2) * Z, D4 = 3.0 * (XY - Z2) * Z2, D5 = XY * Z2 * Z;
     double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D2 * D2 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
                  D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0);
-    double rd = p4 * ser * iAD * rsq64(AD) + 3.0 * sumD;
+    double rd = fma(p4 * ser * iAD, rAD, 3.0 * sumD);
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
 }
 
@@ -407,19 +422,19 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
         E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
         return;
     }
-    double iK = rcp64(K);
-    cy_endpoint(q, P, r, q.d, q.Dad, q.Dbd, iK, E.sa, E.ca, E.da);
-    cy_endpoint(q, P, r, q.c, q.Dac, q.Dbc, iK, E.sb, E.cb, E.db);
+    double isK = rsq64(K);
+    cy_endpoint(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
+    cy_endpoint(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
     if (!(cr > 0.0)) { E.I = 0.0; return; }
-    double nu = P.mu * iK;
+    double nu = P.mu * isK * isK;
     double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
     double idn = rcp64(den);
     double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
     double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
     double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
     double es = ellip_e_scd(ss, cs, ds, nu);
-    E.I = 2.0 * K * rsq64(K) * fma(-nu * E.sb * E.sa, ss, es);
+    E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
 }
 
 // 2 atan(cr / dt) for the small angle between consecutive half angles
@@ -445,7 +460,7 @@ __device__ __forceinline__ double twice_angle(double cr, double dt)
 
 template <class Sink>
 __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, double r0, int wlo, int whi,
-                                         Sink& sink)
+                                         double wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
@@ -456,7 +471,7 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
         double dal = twice_angle(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa));
         double dbe = twice_angle(fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb));
         // Eq. area_D_l_xi, times J0 = R
-        double area = P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
+        double area = wgt * P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
         sink(m, area);
         E0 = E1;
     }

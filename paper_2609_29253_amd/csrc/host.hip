@@ -37,7 +37,7 @@ struct pat_ctx {
     TrDev* d_tr = nullptr;
     int32_t* d_kperm = nullptr;
     double* d_scale = nullptr;
-    void* d_G = nullptr;
+    double* d_G = nullptr;
     double* d_qpts = nullptr;
     double* d_qdA = nullptr;
     double* d_f = nullptr;
@@ -66,7 +66,7 @@ pat_status fail(pat_ctx* c, pat_status st, const std::string& msg)
 
 void free_dev(pat_ctx* c)
 {
-    void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, &c->d_G,
+    void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, (void**)&c->d_G,
                      (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z};
     for (void** p : ptrs) {
         if (*p) (void)hipFree(*p);
@@ -353,7 +353,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         return hipMalloc(ptr, bytes) == hipSuccess;
     };
     if (!dmalloc((void**)&c->d_tr, sizeof(TrDev) * K) || !dmalloc((void**)&c->d_kperm, sizeof(int32_t) * K) ||
-        !dmalloc((void**)&c->d_scale, sizeof(double) * Mcount) || !dmalloc(&c->d_G, rs * jcnt) ||
+        !dmalloc((void**)&c->d_scale, sizeof(double) * Mcount) || !dmalloc((void**)&c->d_G, sizeof(double) * jcnt) ||
         !dmalloc((void**)&c->d_f, fbytes) || !dmalloc(&c->d_W, wbytes) || !dmalloc((void**)&c->d_z, zbytes) ||
         (Q > 0 && (!dmalloc((void**)&c->d_qpts, sizeof(double) * qp.size()) ||
                    !dmalloc((void**)&c->d_qdA, sizeof(double) * K)))) {
@@ -369,12 +369,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     up(c->d_tr, T.data(), sizeof(TrDev) * K);
     up(c->d_kperm, perm.data(), sizeof(int32_t) * K);
     up(c->d_scale, scale.data(), sizeof(double) * Mcount);
-    if (p.precision == PAT_FP64) {
-        up(c->d_G, G.data(), sizeof(double) * jcnt);
-    } else {
-        std::vector<float> Gf(G.begin(), G.end());
-        up(c->d_G, Gf.data(), sizeof(float) * jcnt);
-    }
+    up(c->d_G, G.data(), sizeof(double) * jcnt);
     if (Q > 0) {
         up(c->d_qpts, qp.data(), sizeof(double) * qp.size());
         up(c->d_qdA, qdA.data(), sizeof(double) * K);

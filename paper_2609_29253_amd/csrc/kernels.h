@@ -23,7 +23,8 @@ struct LaunchPlan {
     bool fp64;
     int U, L;
     int jlo, jcnt;          // polyphase filter G[j], j = jlo .. jlo + jcnt - 1
-    const void* G;          // [jcnt] float or double
+    const double* G;        // [jcnt] FP64 in both variants: the zero-mean kernel amplifies any
+                            // rounding of its taps by |h||f|/|h*f| (20-300) in the signal
     const double* scale;    // [Mcount]
     double* f;              // [max_batch][K][Mcount] forward workspace
     void* W;                // [max_batch][K][Mcount] adjoint workspace (float or double)

@@ -8,7 +8,7 @@
 //                        bin of each surface point (Alg. 2, Eq. def_f_point) of an
 //                        LDS FP64 histogram covering the brick's bin window; the
 //                        window is then added to f with FP64 atomics.
-//   3. k_fir             s_hat[l] = sum_j G[j] scale[m] f[m], m = U l - j: the
+//   3. k_fir             s_hat[l] = sum_j G[j] scale[m] f[m], m = U l - j (FP64): the
 //                        convolution with h followed by the block average D_U
 //                        (Eq. discrete_conv, Eq. def_downsampling) as one
 //                        polyphase filter G[j] = 1/U sum_{l'=1..U} h[j + l'];
@@ -113,18 +113,45 @@ __device__ __forceinline__ void frame_coords(const TrDev& T, int ix, int iy, int
 // (Eq. uvminmax; Eq. folded_intervals for the cylinder), built one at a time
 // ---------------------------------------------------------------------------
 
+// Two reflected intervals that share an end point, [e, p] and [e, q] (or [p, e]
+// and [q, e]), cover the same parameter region as the interval between e and
+// the nearer of p, q counted twice plus the remainder counted once.  Sweeping
+// the merged form visits each bin of the shared part once instead of twice.
+struct WInt {
+    double lo[2], hi[2];
+    float w[2];
+    int n;
+};
+
+// intervals [0, A] and [0, B] (A, B >= 0), Eq. uvminmax with the origin inside
+__device__ __forceinline__ void split_at_zero(double A, double B, WInt& I)
+{
+    double m = fmin(A, B), M = fmax(A, B);
+    I.lo[0] = 0.0; I.hi[0] = m; I.w[0] = 2.0f;
+    I.lo[1] = m;   I.hi[1] = M; I.w[1] = 1.0f;
+    I.n = 2;
+}
+
+// the reflected intervals of [lo, hi] about 0 (Eq. uvminmax)
+__device__ __forceinline__ void fold_line(double lo, double hi, WInt& I)
+{
+    if (lo < 0.0 && 0.0 < hi) { split_at_zero(-lo, hi, I); return; }
+    double a = fabs(lo), b = fabs(hi);
+    I.lo[0] = fmin(a, b); I.hi[0] = fmax(a, b); I.w[0] = 1.0f;
+    I.lo[1] = I.hi[1] = 0.0; I.w[1] = 0.0f;
+    I.n = 1;
+}
+
 template <class AT>
 struct PlanarPair {
-    double u[2][2], v[2][2], z2;
+    WInt U, V;
+    double z2;
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
         double L1 = T.p[0], L2 = T.p[1];
-        double u1 = -L1 - x[0], u2 = L1 - x[0], v1 = -L2 - x[1], v2 = L2 - x[1];
+        fold_line(-L1 - x[0], L1 - x[0], U);
+        fold_line(-L2 - x[1], L2 - x[1], V);
         z2 = x[2] * x[2];
-        u[0][0] = fmax(u1, 0.0); u[0][1] = fmax(u2, 0.0);
-        u[1][0] = fmax(-u2, 0.0); u[1][1] = fmax(-u1, 0.0);
-        v[0][0] = fmax(v1, 0.0); v[0][1] = fmax(v2, 0.0);
-        v[1][0] = fmax(-v2, 0.0); v[1][1] = fmax(-v1, 0.0);
     }
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
@@ -132,12 +159,14 @@ struct PlanarPair {
 #pragma unroll 1
         for (int qi = 0; qi < 4; ++qi) {
             const int i = qi >> 1, j = qi & 1;
-            const double a = i ? u[1][0] : u[0][0], b = i ? u[1][1] : u[0][1];
-            const double c = j ? v[1][0] : v[0][0], d = j ? v[1][1] : v[0][1];
+            if (i >= U.n || j >= V.n) continue;
+            const double a = i ? U.lo[1] : U.lo[0], b = i ? U.hi[1] : U.hi[0];
+            const double c = j ? V.lo[1] : V.lo[0], d = j ? V.hi[1] : V.hi[0];
             if (!(b > a) || !(d > c)) continue;
+            const float w = (i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]);
             PlQuad<AT> q;
             pl_setup(q, a, b, c, d, z2, r0);
-            pl_sweep(q, wlo, whi, sink);
+            pl_sweep(q, wlo, whi, (AT)w, sink);
         }
     }
 };
@@ -152,8 +181,7 @@ __device__ __forceinline__ double wrap_pi(double u)
 }
 
 struct CylinderPair {
-    double u[2][2], v[2][2];
-    int nu;
+    WInt U, V;
     CyPair P;
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
@@ -163,16 +191,23 @@ struct CylinderPair {
         P.R = R;
         P.dm = fabs(R - rho);
         P.mu = 4.0 * R * rho;
-        P.inv_mu = P.mu > 0.0 ? 1.0 / P.mu : 0.0;
+        P.isq_mu = P.mu > 0.0 ? rsq64(P.mu) : 0.0;
         double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
         // Eq. folded_intervals
-        if (u1 < 0.0 && 0.0 < u2) { u[0][0] = 0.0; u[0][1] = -u1; u[1][0] = 0.0; u[1][1] = u2; nu = 2; }
-        else if (u2 < u1) { u[0][0] = u1; u[0][1] = M_PI; u[1][0] = -u2; u[1][1] = M_PI; nu = 2; }
-        else if (0.0 <= u1) { u[0][0] = u1; u[0][1] = u2; u[1][0] = u[1][1] = 0.0; nu = 1; }
-        else { u[0][0] = -u2; u[0][1] = -u1; u[1][0] = u[1][1] = 0.0; nu = 1; }
-        double v1 = -Lz - x[2], v2 = Lz - x[2];
-        v[0][0] = fmax(v1, 0.0); v[0][1] = fmax(v2, 0.0);
-        v[1][0] = fmax(-v2, 0.0); v[1][1] = fmax(-v1, 0.0);
+        if (u1 < 0.0 && 0.0 < u2) {
+            split_at_zero(-u1, u2, U);
+        } else if (u2 < u1) {
+            // [u1, pi] and [-u2, pi]
+            double m = fmax(u1, -u2), M = fmin(u1, -u2);
+            U.lo[0] = m; U.hi[0] = M_PI; U.w[0] = 2.0f;
+            U.lo[1] = M; U.hi[1] = m;    U.w[1] = 1.0f;
+            U.n = 2;
+        } else if (0.0 <= u1) {
+            U.lo[0] = u1; U.hi[0] = u2; U.w[0] = 1.0f; U.n = 1;
+        } else {
+            U.lo[0] = -u2; U.hi[0] = -u1; U.w[0] = 1.0f; U.n = 1;
+        }
+        fold_line(-Lz - x[2], Lz - x[2], V);
     }
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
@@ -180,13 +215,14 @@ struct CylinderPair {
 #pragma unroll 1
         for (int qi = 0; qi < 4; ++qi) {
             const int i = qi >> 1, j = qi & 1;
-            if (i >= nu) break;
-            const double a = i ? u[1][0] : u[0][0], b = i ? u[1][1] : u[0][1];
-            const double c = j ? v[1][0] : v[0][0], d = j ? v[1][1] : v[0][1];
+            if (i >= U.n || j >= V.n) continue;
+            const double a = i ? U.lo[1] : U.lo[0], b = i ? U.hi[1] : U.hi[0];
+            const double c = j ? V.lo[1] : V.lo[0], d = j ? V.hi[1] : V.hi[0];
             if (!(b > a) || !(d > c)) continue;
+            const double w = (double)((i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]));
             CyQuad q;
             cy_setup(q, P, a, b, c, d, r0);
-            cy_sweep(q, P, r0, wlo, whi, sink);
+            cy_sweep(q, P, r0, wlo, whi, w, sink);
         }
     }
 };
@@ -497,26 +533,28 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
 
 // s_hat[b][k][l] = sum_j G[j] scale[m] f[b][k][m],  m = U l - (jlo + jj)  (0-based l)
 template <class Real>
-__global__ void k_fir(const double* __restrict__ f, const double* __restrict__ scale, const Real* __restrict__ G,
+__global__ void k_fir(const double* __restrict__ f, const double* __restrict__ scale, const double* __restrict__ G,
                       int jlo, int jcnt, int U, int L, int K, int64_t Mlo, int64_t Mcount, Real* __restrict__ out)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y, b = blockIdx.z;
     if (l >= L) return;
     const double* fk = f + ((int64_t)b * K + k) * Mcount;
-    Real acc = Real(0);
+    // h sums to zero, so the samples are small differences of large terms:
+    // accumulated in FP64
+    double acc = 0.0;
     const int64_t mtop = (int64_t)U * l - jlo;   // m for jj = 0
     for (int jj = 0; jj < jcnt; ++jj) {
         int64_t mi = mtop - jj - Mlo;
         if (mi < 0 || mi >= Mcount) continue;
-        acc = fma(G[jj], (Real)(scale[mi] * fk[mi]), acc);
+        acc = fma(G[jj], scale[mi] * fk[mi], acc);
     }
-    out[((int64_t)b * K + k) * L + l] = acc;
+    out[((int64_t)b * K + k) * L + l] = (Real)acc;
 }
 
 // W[b][k][m] = scale[m] sum_l G[U l - m] y[b][k][l]
 template <class Real>
-__global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ scale, const Real* __restrict__ G,
+__global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ scale, const double* __restrict__ G,
                        int jlo, int jcnt, int U, int L, int K, int64_t Mlo, int64_t Mcount, Real* __restrict__ W)
 {
     const int64_t mi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -529,9 +567,9 @@ __global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ sc
     int lmax = floordiv(m + jlo + jcnt - 1, U);
     lmin = max(lmin, 0);
     lmax = min(lmax, L - 1);
-    Real acc = Real(0);
-    for (int l = lmin; l <= lmax; ++l) acc = fma(G[U * l - m - jlo], yk[l], acc);
-    W[((int64_t)b * K + k) * Mcount + mi] = (Real)scale[mi] * acc;
+    double acc = 0.0;
+    for (int l = lmin; l <= lmax; ++l) acc = fma(G[U * l - m - jlo], (double)yk[l], acc);
+    W[((int64_t)b * K + k) * Mcount + mi] = (Real)(scale[mi] * acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,7 +670,7 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
         b0 += nb;
     }
     dim3 g2((L.L + 255) / 256, L.base.K, B);
-    k_fir<Real><<<g2, 256, 0, s>>>(L.f, L.scale, (const Real*)L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
+    k_fir<Real><<<g2, 256, 0, s>>>(L.f, L.scale, L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
                                    L.base.Mlo, L.base.Mcount, sig);
     return hipGetLastError();
 }
@@ -643,7 +681,7 @@ hipError_t adjoint_t(const LaunchPlan& L, const Real* sig, Real* coef, int B, hi
     hipError_t e;
     Real* W = (Real*)L.W;
     dim3 g1((unsigned)((L.base.Mcount + 255) / 256), L.base.K, B);
-    k_adjw<Real><<<g1, 256, 0, s>>>(sig, L.scale, (const Real*)L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
+    k_adjw<Real><<<g1, 256, 0, s>>>(sig, L.scale, L.G, L.jlo, L.jcnt, L.U, L.L, L.base.K,
                                     L.base.Mlo, L.base.Mcount, W);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     bool direct = L.ngroups == 1 && L.groups[0].kchunk_adj >= L.groups[0].nk;

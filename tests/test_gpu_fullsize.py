@@ -1,0 +1,77 @@
+"""Full-size workloads on the GPU (the launch configuration bench.py times),
+checked against the FP64 oracle on sampled outputs it can compute one by one:
+the signals of a few transducers over every voxel, and the adjoint at a few
+thousand voxels over every transducer.  Dot tests use every output.
+
+Tolerances: FP32 1e-5 relative L2 per sampled output set (and per volume for
+the batched workload).  FP64 2e-9: at full size the oracle and the FP64 kernels
+are two independent FP64 evaluations of the closed forms, each carrying ~1e-12
+relative rounding per bin in the cylinder (differences of nearly equal
+elliptic integrals), and the zero-mean system kernel amplifies relative errors
+of the fine-bin coefficients by 20-300 (the ratio |h| |f| / |h * f|).
+The dot test is normalised by |A p| |y| (y is white noise, so <A p, y> itself
+is ~sqrt(K L) times smaller than that bound).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import pat_inputs as P
+from conftest import rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL = {"fp32": 1e-5, "fp64": 2e-9}
+DT = {"fp32": torch.float32, "fp64": torch.float64}
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        p = {"cfg2": P.config2, "cfg3": P.config3, "cfg5": P.config5}[name]()
+        _cache[name] = {"p": p}
+    return _cache[name]
+
+
+def oracle_samples(name, ks, vs):
+    c = problem(name)
+    key = ("ref", tuple(ks), len(vs))
+    if key not in c:
+        p = c["p"]
+        print(f"[{name}] oracle forward on transducers {list(ks)} and adjoint on {len(vs)} voxels", flush=True)
+        c[key] = (O.forward(p, ksub=np.asarray(ks, dtype=np.int32)), O.adjoint(p, vsub=vs))
+    return c[key]
+
+
+def gpu_full(name, prec):
+    from paper_2609_29253_amd.operator import PatOperator
+    p = problem(name)["p"]
+    B = p.coef.shape[0]
+    dev = torch.device("cuda", 0)
+    op = PatOperator.from_problem(p, mode="closed", precision=prec, max_batch=B)
+    assert op.query(4) == 0.0, "window truncates arrivals"
+    s = op.forward(torch.tensor(p.coef, dtype=DT[prec], device=dev))
+    z = op.adjoint(torch.tensor(p.y, dtype=DT[prec], device=dev))
+    torch.cuda.synchronize()
+    out = s.double().cpu().numpy(), z.double().cpu().numpy()
+    op.close()
+    return p, out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,ks", [("cfg2", [0, 131]), ("cfg3", [0, 300]), ("cfg5", [0, 77])])
+def test_fullsize_sampled_parity(gpu, name, ks, prec):
+    p, (s, z) = gpu_full(name, prec)
+    vs = np.linspace(0, p.N - 1, 3000).astype(np.int64)
+    s_ref, z_ref = oracle_samples(name, ks, vs)
+    for b in range(p.coef.shape[0]):
+        es = rel_l2(s[b, ks], s_ref[b])
+        ez = rel_l2(z[b, vs], z_ref[b])
+        print(f"[{name} {prec}] volume {b}: forward {es:.3e} adjoint {ez:.3e}", flush=True)
+        assert es < TOL[prec] and ez < TOL[prec]
+    # dot test over every output, reductions in FP64
+    lhs, rhs = float(np.sum(s * p.y)), float(np.sum(z * p.coef))
+    gap = abs(lhs - rhs) / (np.linalg.norm(s) * np.linalg.norm(p.y))
+    print(f"[{name} {prec}] <Ap,y> = {lhs:.10e}, <p,A^T y> = {rhs:.10e}, normalised gap {gap:.3e}", flush=True)
+    assert gap < (1e-6 if prec == "fp32" else 1e-13)
