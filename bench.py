@@ -87,7 +87,10 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--calib", action="store_true",
+                    help="copy a 256 MiB device buffer first (reference kernel for HBM counters)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one forward and one adjoint of the closed FP32 variant, nothing else")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator is built and timed on a single MI355X; "
@@ -103,6 +106,13 @@ def main():
     log(f"[bench] workload {prob.name}: N={prob.N} K={prob.K} L={prob.L} B={prob.coef.shape[0]} "
         f"({time.perf_counter() - t_build:.1f}s to generate)")
     dev = torch.device("cuda", 0)
+    if args.calib:
+        xa = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+        xb = torch.empty_like(xa)
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del xa, xb
     kern = build_kernel(prob.phi_type, prob.kappa, prob.eir, prob.sound_speed, prob.fs, prob.U)
     B = prob.coef.shape[0]
     pairs = float(B) * prob.N * prob.K
@@ -128,6 +138,16 @@ def main():
             f"{out['pairs_per_s']:.3e} pairs/s, {evals:.3e} area evaluations per volume")
         return out
 
+    if args.profile_only:
+        op = PatOperator.from_problem(prob, mode="closed", precision="fp32", max_batch=B, kernel=kern)
+        coef = torch.tensor(prob.coef, dtype=torch.float32, device=dev)
+        y = torch.tensor(prob.y, dtype=torch.float32, device=dev)
+        op.forward(coef)
+        op.adjoint(y)
+        torch.cuda.synchronize()
+        log(f"[bench] profile run done: one A and one A^T of {prob.name}")
+        op.close()
+        return
     main_res = run_variant("closed", "fp32", args.steps, args.warmup)
     results["closed_fp32"] = main_res
     if not args.no_variants:

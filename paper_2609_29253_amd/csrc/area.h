@@ -55,16 +55,22 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// v_rsq_f64 is accurate to ~2^-24: each Newton step doubles the correct bits
+// (one step: ~2^-48, two: full precision)
+template <int NEWTON = 2>
 __device__ __forceinline__ double rsq64(double x)
 {
     double r = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x * r;
-    r = fma(r, fma(-h, r, 0.5), r);
-    h = 0.5 * x * r;
-    return fma(r, fma(-h, r, 0.5), r);
+#pragma unroll
+    for (int i = 0; i < NEWTON; ++i) {
+        double h = 0.5 * x * r;
+        r = fma(r, fma(-h, r, 0.5), r);
+    }
+    return r;
 }
 
-__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsq64(x) : 0.0; }
+template <int NEWTON = 2>
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsq64<NEWTON>(x) : 0.0; }
 
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt64(x); }
@@ -351,6 +357,7 @@ __device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, d
 
 // one end point of the level curve on the line v (Eq. alphabeta), half-angle form;
 // isK = 1/sqrt(r^2 - (R - rho)^2)
+template <int NW>
 __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, double r, double v,
                                             double Dav, double Dbv, double isK, double& s, double& c,
                                             double& dl)
@@ -358,22 +365,23 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
     double qa = (r - Dav) * (r + Dav);          // r^2 - v^2 - psi(a)
     if (!(qa > 0.0)) {
         s = q.sa; c = q.ca;
-        dl = sqrt64((r - q.Da0) * (r + q.Da0)) * isK;
+        dl = sqrt64<NW>((r - q.Da0) * (r + q.Da0)) * isK;
         return;
     }
     double qb = (r - Dbv) * (r + Dbv);          // r^2 - v^2 - psi(b)
     if (!(qb < 0.0)) {
         s = q.sb; c = q.cb;
-        dl = sqrt64((r - q.Db0) * (r + q.Db0)) * isK;
+        dl = sqrt64<NW>((r - q.Db0) * (r + q.Db0)) * isK;
         return;
     }
-    s = sqrt64(qa + q.musa2) * P.isq_mu;
-    c = sqrt64(q.mucb2 - qb) * P.isq_mu;
+    s = sqrt64<NW>(qa + q.musa2) * P.isq_mu;
+    c = sqrt64<NW>(q.mucb2 - qb) * P.isq_mu;
     dl = v * isK;
 }
 
 // E(sigma, nu) from sin, cos and Delta of sigma (Carlson's duplication with the
 // stopping rule of Carlson 1995 for a relative tolerance of 1e-13; DLMF 19.36.1-2)
+template <int NW>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu)
 {
     double x = c * c, y = dl * dl, z = 1.0;
@@ -394,15 +402,15 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
         AF = 0.25 * (AF + lam);
         AD = 0.25 * (AD + lam);
         p4 *= 0.25;
-        sx = sqrt64(x);
-        sy = sqrt64(y);
-        sz = sqrt64(z);
+        sx = sqrt64<NW>(x);
+        sy = sqrt64<NW>(y);
+        sz = sqrt64<NW>(z);
     }
-    double rAF = rsq64(AF), iAF = rAF * rAF;
+    double rAF = rsq64<NW>(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
     double rf = (1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0)) * rAF;
-    double rAD = rsq64(AD), iAD = rAD * rAD;
+    double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
     Y = (AD - y) * iAD;
     Z = -(X + Y) * (1.0 / 3.0);
@@ -415,6 +423,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
 }
 
 // Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I (Eq. cyl_Il)
+template <int NW>
 __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
 {
     double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
@@ -422,9 +431,9 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
         E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
         return;
     }
-    double isK = rsq64(K);
-    cy_endpoint(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
-    cy_endpoint(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
+    double isK = rsq64<NW>(K);
+    cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
+    cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
     if (!(cr > 0.0)) { E.I = 0.0; return; }
     double nu = P.mu * isK * isK;
@@ -433,7 +442,7 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
     double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
     double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
-    double es = ellip_e_scd(ss, cs, ds, nu);
+    double es = ellip_e_scd<NW>(ss, cs, ds, nu);
     E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
 }
 
@@ -458,16 +467,16 @@ __device__ __forceinline__ double twice_angle(double cr, double dt)
     return 2.0 * fma(-x * y, p, x);
 }
 
-template <class Sink>
+template <int NW, class Sink>
 __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, double r0, int wlo, int whi,
                                          double wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
     CyEdge E0, E1;
-    cy_edge(q, P, r0 + (mb - 1), E0);
+    cy_edge<NW>(q, P, r0 + (mb - 1), E0);
     for (int m = mb; m <= me; ++m) {
-        cy_edge(q, P, r0 + m, E1);
+        cy_edge<NW>(q, P, r0 + m, E1);
         double dal = twice_angle(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa));
         double dbe = twice_angle(fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb));
         // Eq. area_D_l_xi, times J0 = R

@@ -156,13 +156,22 @@ struct PlanarPair {
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
-#pragma unroll 1
+        // the lane's non-empty quadrants first, so lanes step through their k-th
+        // quadrant together
+        int list = 0, nq = 0;
+#pragma unroll
         for (int qi = 0; qi < 4; ++qi) {
             const int i = qi >> 1, j = qi & 1;
-            if (i >= U.n || j >= V.n) continue;
+            const bool ok = i < U.n && j < V.n && (i ? U.hi[1] > U.lo[1] : U.hi[0] > U.lo[0]) &&
+                            (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
+            if (ok) { list |= qi << (2 * nq); ++nq; }
+        }
+#pragma unroll 1
+        for (int t = 0; t < nq; ++t) {
+            const int qi = (list >> (2 * t)) & 3;
+            const int i = qi >> 1, j = qi & 1;
             const double a = i ? U.lo[1] : U.lo[0], b = i ? U.hi[1] : U.hi[0];
             const double c = j ? V.lo[1] : V.lo[0], d = j ? V.hi[1] : V.hi[0];
-            if (!(b > a) || !(d > c)) continue;
             const float w = (i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]);
             PlQuad<AT> q;
             pl_setup(q, a, b, c, d, z2, r0);
@@ -180,6 +189,7 @@ __device__ __forceinline__ double wrap_pi(double u)
     return u;
 }
 
+template <int NW>
 struct CylinderPair {
     WInt U, V;
     CyPair P;
@@ -212,24 +222,34 @@ struct CylinderPair {
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
-#pragma unroll 1
+        int list = 0, nq = 0;
+#pragma unroll
         for (int qi = 0; qi < 4; ++qi) {
             const int i = qi >> 1, j = qi & 1;
-            if (i >= U.n || j >= V.n) continue;
+            const bool ok = i < U.n && j < V.n && (i ? U.hi[1] > U.lo[1] : U.hi[0] > U.lo[0]) &&
+                            (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
+            if (ok) { list |= qi << (2 * nq); ++nq; }
+        }
+#pragma unroll 1
+        for (int t = 0; t < nq; ++t) {
+            const int qi = (list >> (2 * t)) & 3;
+            const int i = qi >> 1, j = qi & 1;
             const double a = i ? U.lo[1] : U.lo[0], b = i ? U.hi[1] : U.hi[0];
             const double c = j ? V.lo[1] : V.lo[0], d = j ? V.hi[1] : V.hi[0];
-            if (!(b > a) || !(d > c)) continue;
             const double w = (double)((i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]));
             CyQuad q;
             cy_setup(q, P, a, b, c, d, r0);
-            cy_sweep(q, P, r0, wlo, whi, w, sink);
+            cy_sweep<NW>(q, P, r0, wlo, whi, w, sink);
         }
     }
 };
 
 template <int SHAPE, class AT> struct PairOf;
 template <class AT> struct PairOf<0, AT> { using type = PlanarPair<AT>; };
-template <class AT> struct PairOf<1, AT> { using type = CylinderPair; };
+// cylinder areas are FP64 in both variants; the FP32 variant needs ~1e-12 in
+// the elliptic differences and takes one Newton step after v_rsq_f64 (2^-48)
+template <> struct PairOf<1, float> { using type = CylinderPair<1>; };
+template <> struct PairOf<1, double> { using type = CylinderPair<2>; };
 
 // ---------------------------------------------------------------------------
 // forward, closed-form areas
