@@ -69,11 +69,17 @@ __device__ __forceinline__ double rsq64(double x)
     return r;
 }
 
+// sqrt(max(x, 1e-300)): branch free; returns 1e-150 instead of 0 for x <= 0,
+// which is below any length or cosine that enters a sum here
 template <int NEWTON = 2>
-__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsq64<NEWTON>(x) : 0.0; }
+__device__ __forceinline__ double sqrt64(double x)
+{
+    x = fmax(x, 1e-300);
+    return x * rsq64<NEWTON>(x);
+}
 
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
-__device__ __forceinline__ double sqrt_t(double x) { return sqrt64(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return x > 0.0 ? x * rsq64(x) : 0.0; }
 // atan2 for y, x >= 0.  Small angles (y <= x/5) take the odd Taylor series of
 // atan(y/x), whose error is the rounding of a few correctly rounded operations;
 // the library routine's error, a smooth function of its argument, would be
@@ -379,8 +385,11 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
     dl = v * isK;
 }
 
-// E(sigma, nu) from sin, cos and Delta of sigma (Carlson's duplication with the
-// stopping rule of Carlson 1995 for a relative tolerance of 1e-13; DLMF 19.36.1-2)
+// E(sigma, nu) from sin, cos and Delta of sigma: E = s R_F(c^2, D^2, 1) -
+// nu s^3 R_D(c^2, D^2, 1) / 3 (DLMF 19.25.9), with Carlson's duplication and
+// the series of DLMF 19.36.1-2 through degree 7.  Their truncation error is
+// ~eps^8 / 4 for eps = max |1 - x_i / A|, so the duplication stops once
+// eps < 1/35 (relative error ~1e-13).
 template <int NW>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu)
 {
@@ -390,7 +399,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double AD = (x + y + 3.0 * z) * 0.2;
     double dev = fmax(fabs(AF - x), fmax(fabs(AF - y), fabs(AF - z)));
     dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
-    const double Qf = 125.0;   // (3 * 1e-13)^(-1/6)
+    const double Qf = 35.0;
     double p4 = 1.0, sumD = 0.0;
 #pragma unroll 1
     for (int it = 0; it < 12 && p4 * Qf * dev >= fmin(AF, AD); ++it) {
@@ -409,15 +418,20 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double rAF = rsq64<NW>(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
-    double rf = (1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E2 * E2 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0)) * rAF;
+    double E22 = E2 * E2;
+    double sf = 1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E22 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0) -
+                E22 * E2 * (5.0 / 208.0) + E3 * E3 * (3.0 / 104.0) + E22 * E3 * (1.0 / 16.0);
+    double rf = sf * rAF;
     double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
     Y = (AD - y) * iAD;
     Z = -(X + Y) * (1.0 / 3.0);
     double XY = X * Y, Z2 = Z * Z;
     double D2 = XY - 6.0 * Z2, D3 = (3.0 * XY - 8.0 * Z2) * Z, D4 = 3.0 * (XY - Z2) * Z2, D5 = XY * Z2 * Z;
-    double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D2 * D2 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
-                 D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0);
+    double D22 = D2 * D2;
+    double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D22 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
+                 D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0) - D22 * D2 * (1.0 / 16.0) + D3 * D3 * (3.0 / 40.0) +
+                 D2 * D4 * (3.0 / 20.0) + D22 * D3 * (45.0 / 272.0) - (D3 * D4 + D2 * D5) * (9.0 / 68.0);
     double rd = fma(p4 * ser * iAD, rAD, 3.0 * sumD);
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
 }
@@ -446,25 +460,44 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
 }
 
-// 2 atan(cr / dt) for the small angle between consecutive half angles
-__device__ __forceinline__ double twice_angle(double cr, double dt)
+// 2 atan(x), 0 <= x <= 0.2, odd Taylor series: through x^23 below 0.2, through
+// x^11 below 0.05 (the first omitted term is then < 2e-17 relative)
+template <bool SHORT>
+__device__ __forceinline__ double twice_atan_small(double x)
 {
-    if (!(cr > 0.0)) return 0.0;
-    double x = cr * rcp64(dt);
-    if (x > 0.2) return 2.0 * atan2(cr, dt);
-    double y = x * x;
-    double p = 1.0 / 23;
-    p = fma(y, p, -1.0 / 21);
-    p = fma(y, p, 1.0 / 19);
-    p = fma(y, p, -1.0 / 17);
-    p = fma(y, p, 1.0 / 15);
-    p = fma(y, p, -1.0 / 13);
-    p = fma(y, p, 1.0 / 11);
+    double y = x * x, p;
+    if (SHORT) {
+        p = 1.0 / 11;
+    } else {
+        p = 1.0 / 23;
+        p = fma(y, p, -1.0 / 21);
+        p = fma(y, p, 1.0 / 19);
+        p = fma(y, p, -1.0 / 17);
+        p = fma(y, p, 1.0 / 15);
+        p = fma(y, p, -1.0 / 13);
+        p = fma(y, p, 1.0 / 11);
+    }
     p = fma(y, p, -1.0 / 9);
     p = fma(y, p, 1.0 / 7);
     p = fma(y, p, -1.0 / 5);
     p = fma(y, p, 1.0 / 3);
     return 2.0 * fma(-x * y, p, x);
+}
+
+// the angle steps 2 atan(cr / dt) of both end points between consecutive edges;
+// the short series is taken when every active lane of the wave allows it
+__device__ __forceinline__ void twice_angles(double cra, double dta, double crb, double dtb, double& da,
+                                             double& db)
+{
+    const double xa = cra > 0.0 ? cra * rcp64(dta) : 0.0;
+    const double xb = crb > 0.0 ? crb * rcp64(dtb) : 0.0;
+    if (__all(fmax(xa, xb) <= 0.05)) {
+        da = twice_atan_small<true>(xa);
+        db = twice_atan_small<true>(xb);
+        return;
+    }
+    da = xa > 0.2 ? 2.0 * atan2(cra, dta) : twice_atan_small<false>(xa);
+    db = xb > 0.2 ? 2.0 * atan2(crb, dtb) : twice_atan_small<false>(xb);
 }
 
 template <int NW, class Sink>
@@ -477,8 +510,9 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
     cy_edge<NW>(q, P, r0 + (mb - 1), E0);
     for (int m = mb; m <= me; ++m) {
         cy_edge<NW>(q, P, r0 + m, E1);
-        double dal = twice_angle(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa));
-        double dbe = twice_angle(fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb));
+        double dal, dbe;
+        twice_angles(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa),
+                     fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb), dal, dbe);
         // Eq. area_D_l_xi, times J0 = R
         double area = wgt * P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
         sink(m, area);

@@ -219,10 +219,11 @@ struct CylinderPair {
         }
         fold_line(-Lz - x[2], Lz - x[2], V);
     }
-    template <class Sink>
-    __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
+    // the non-empty quadrants (2 bits each, in sweep order) and their number
+    __device__ __forceinline__ int quadrants(int& nq) const
     {
-        int list = 0, nq = 0;
+        int list = 0;
+        nq = 0;
 #pragma unroll
         for (int qi = 0; qi < 4; ++qi) {
             const int i = qi >> 1, j = qi & 1;
@@ -230,13 +231,26 @@ struct CylinderPair {
                             (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
             if (ok) { list |= qi << (2 * nq); ++nq; }
         }
+        return list;
+    }
+    __device__ __forceinline__ void quadrant(int qi, double& a, double& b, double& c, double& d, double& w) const
+    {
+        const int i = qi >> 1, j = qi & 1;
+        a = i ? U.lo[1] : U.lo[0]; b = i ? U.hi[1] : U.hi[0];
+        c = j ? V.lo[1] : V.lo[0]; d = j ? V.hi[1] : V.hi[0];
+        w = (double)((i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]));
+    }
+    template <class Sink>
+    __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
+    {
+        // the lane's non-empty quadrants first, so lanes step through their k-th
+        // quadrant together
+        int nq;
+        const int list = quadrants(nq);
 #pragma unroll 1
         for (int t = 0; t < nq; ++t) {
-            const int qi = (list >> (2 * t)) & 3;
-            const int i = qi >> 1, j = qi & 1;
-            const double a = i ? U.lo[1] : U.lo[0], b = i ? U.hi[1] : U.hi[0];
-            const double c = j ? V.lo[1] : V.lo[0], d = j ? V.hi[1] : V.hi[0];
-            const double w = (double)((i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]));
+            double a, b, c, d, w;
+            quadrant((list >> (2 * t)) & 3, a, b, c, d, w);
             CyQuad q;
             cy_setup(q, P, a, b, c, d, r0);
             cy_sweep<NW>(q, P, r0, wlo, whi, w, sink);
@@ -244,12 +258,15 @@ struct CylinderPair {
     }
 };
 
-template <int SHAPE, class AT> struct PairOf;
-template <class AT> struct PairOf<0, AT> { using type = PlanarPair<AT>; };
-// cylinder areas are FP64 in both variants; the FP32 variant needs ~1e-12 in
-// the elliptic differences and takes one Newton step after v_rsq_f64 (2^-48)
-template <> struct PairOf<1, float> { using type = CylinderPair<1>; };
-template <> struct PairOf<1, double> { using type = CylinderPair<2>; };
+// Cylinder areas are FP64 in both variants.  With FP32 input and output the
+// elliptic differences need ~1e-12, and one Newton step after v_rsq_f64
+// (relative error 2^-48) is enough; the FP64 variant takes two.
+template <class Real> struct CylNewton { static constexpr int value = 2; };
+template <> struct CylNewton<float> { static constexpr int value = 1; };
+
+template <int SHAPE, class AT, class Real> struct PairOf;
+template <class AT, class Real> struct PairOf<0, AT, Real> { using type = PlanarPair<AT>; };
+template <class AT, class Real> struct PairOf<1, AT, Real> { using type = CylinderPair<CylNewton<Real>::value>; };
 
 // ---------------------------------------------------------------------------
 // forward, closed-form areas
@@ -286,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_closed(KParams P, const Real* 
             if (nz) {
                 double x[3];
                 frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT>::type pair;
+                typename PairOf<SHAPE, AT, Real>::type pair;
                 pair.setup(T, x, P.r0);
                 auto sink = [&](int m, auto area) {
 #pragma unroll
@@ -341,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_closed(KParams P, const Real* 
             if (Bk.valid) {
                 double x[3];
                 frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT>::type pair;
+                typename PairOf<SHAPE, AT, Real>::type pair;
                 pair.setup(T, x, P.r0);
                 AT part[NB];
 #pragma unroll
@@ -531,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
             const int lo = (int)P.Mlo, hi = (int)(P.Mlo + P.Mcount - 1);
             int nb = 0;
             auto sink = [&](int, auto) { ++nb; };
-            typename PairOf<SHAPE, double>::type pair;
+            typename PairOf<SHAPE, double, double>::type pair;
             pair.setup(T, x, P.r0);
             pair.sweep(lo, hi, sink, P.r0);
             evals += nb;
