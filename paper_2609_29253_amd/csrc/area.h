@@ -460,23 +460,17 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
 }
 
-// 2 atan(x), 0 <= x <= 0.2, odd Taylor series: through x^23 below 0.2, through
-// x^11 below 0.05 (the first omitted term is then < 2e-17 relative)
-template <bool SHORT>
+// 2 atan(x) for 0 <= x <= 0.2: odd Taylor series through x^23
 __device__ __forceinline__ double twice_atan_small(double x)
 {
-    double y = x * x, p;
-    if (SHORT) {
-        p = 1.0 / 11;
-    } else {
-        p = 1.0 / 23;
-        p = fma(y, p, -1.0 / 21);
-        p = fma(y, p, 1.0 / 19);
-        p = fma(y, p, -1.0 / 17);
-        p = fma(y, p, 1.0 / 15);
-        p = fma(y, p, -1.0 / 13);
-        p = fma(y, p, 1.0 / 11);
-    }
+    double y = x * x;
+    double p = 1.0 / 23;
+    p = fma(y, p, -1.0 / 21);
+    p = fma(y, p, 1.0 / 19);
+    p = fma(y, p, -1.0 / 17);
+    p = fma(y, p, 1.0 / 15);
+    p = fma(y, p, -1.0 / 13);
+    p = fma(y, p, 1.0 / 11);
     p = fma(y, p, -1.0 / 9);
     p = fma(y, p, 1.0 / 7);
     p = fma(y, p, -1.0 / 5);
@@ -484,20 +478,36 @@ __device__ __forceinline__ double twice_atan_small(double x)
     return 2.0 * fma(-x * y, p, x);
 }
 
-// the angle steps 2 atan(cr / dt) of both end points between consecutive edges;
-// the short series is taken when every active lane of the wave allows it
+// asin(u) for 0 <= u <= 0.05: odd Taylor series through u^11 (the first
+// omitted term is < 5e-18 relative)
+__device__ __forceinline__ double asin_small(double u)
+{
+    double y = u * u;
+    double p = 63.0 / 2816;
+    p = fma(y, p, 35.0 / 1152);
+    p = fma(y, p, 5.0 / 112);
+    p = fma(y, p, 3.0 / 40);
+    p = fma(y, p, 1.0 / 6);
+    return fma(u * y, p, u);
+}
+
+// The steps of both end-point angles between consecutive edges, from the sine
+// cr and cosine dt of the half-angle step (negative steps count as zero).  When
+// every active lane of the wave has a small step with dt > 0 the step is
+// 2 asin(cr), with no division; otherwise 2 atan(cr / dt).
 __device__ __forceinline__ void twice_angles(double cra, double dta, double crb, double dtb, double& da,
                                              double& db)
 {
-    const double xa = cra > 0.0 ? cra * rcp64(dta) : 0.0;
-    const double xb = crb > 0.0 ? crb * rcp64(dtb) : 0.0;
-    if (__all(fmax(xa, xb) <= 0.05)) {
-        da = twice_atan_small<true>(xa);
-        db = twice_atan_small<true>(xb);
+    const double ua = fmax(cra, 0.0), ub = fmax(crb, 0.0);
+    if (__all(fmax(ua, ub) <= 0.05 && dta > 0.0 && dtb > 0.0)) {
+        da = 2.0 * asin_small(ua);
+        db = 2.0 * asin_small(ub);
         return;
     }
-    da = xa > 0.2 ? 2.0 * atan2(cra, dta) : twice_atan_small<false>(xa);
-    db = xb > 0.2 ? 2.0 * atan2(crb, dtb) : twice_atan_small<false>(xb);
+    const double xa = cra > 0.0 ? cra * rcp64(dta) : 0.0;
+    const double xb = crb > 0.0 ? crb * rcp64(dtb) : 0.0;
+    da = (xa > 0.2 || !(dta > 0.0)) ? (cra > 0.0 ? 2.0 * atan2(cra, dta) : 0.0) : twice_atan_small(xa);
+    db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2(crb, dtb) : 0.0) : twice_atan_small(xb);
 }
 
 template <int NW, class Sink>

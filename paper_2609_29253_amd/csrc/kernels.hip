@@ -66,10 +66,13 @@ __device__ __forceinline__ void brick_setup(const KParams& P, Brick& Bk)
     const int bid = blockIdx.x;
     const int bxi = bid % P.nbx, byi = (bid / P.nbx) % P.nby, bzi = bid / (P.nbx * P.nby);
     const int x0 = bxi * kBrickX, y0 = byi * kBrickY, z0 = bzi * kBrickZ;
-    const int v = threadIdx.x;
-    Bk.ix = x0 + v % kBrickX;
-    Bk.iy = y0 + (v / kBrickX) % kBrickY;
-    Bk.iz = z0 + v / (kBrickX * kBrickY);
+    // each wave owns a 4 x 4 x 4 sub-cube of the brick: the most compact set of
+    // 64 voxels, so that their sweeps over a transducer have similar lengths
+    // and quadrant counts (less divergence than an 8 x 8 x 1 slab)
+    const int v = threadIdx.x, w = v >> 6, l = v & 63;
+    Bk.ix = x0 + (w & 1) * 4 + (l & 3);
+    Bk.iy = y0 + (w >> 1) * 4 + ((l >> 2) & 3);
+    Bk.iz = z0 + (l >> 4);
     Bk.valid = Bk.ix < P.n[0] && Bk.iy < P.n[1] && Bk.iz < P.n[2];
     Bk.idx = Bk.valid ? Bk.ix + P.n[0] * (Bk.iy + P.n[1] * (int64_t)Bk.iz) : 0;
     const int x1 = (int)min((int64_t)(x0 + kBrickX), P.n[0]) - 1;
@@ -273,7 +276,7 @@ template <class AT, class Real> struct PairOf<1, AT, Real> { using type = Cylind
 // ---------------------------------------------------------------------------
 
 template <int SHAPE, class AT, int NB, class Real>
-__global__ __launch_bounds__(kThreads) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
+__global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
     extern __shared__ double hist[];   // [NB][kHist]
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_closed(KParams P, const Real* 
 // ---------------------------------------------------------------------------
 
 template <int SHAPE, class AT, int NB, class Real>
-__global__ __launch_bounds__(kThreads) void k_adj_closed(KParams P, const Real* __restrict__ W,
+__global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Real* __restrict__ W,
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
 {

@@ -16,6 +16,7 @@ constexpr int kBrickX = 8;         // voxel brick owned by one work-group, one v
 constexpr int kBrickY = 8;
 constexpr int kBrickZ = 4;
 static_assert(kBrickX * kBrickY * kBrickZ == kThreads, "one voxel per thread");
+static_assert(kBrickX == 8 && kBrickY == 8 && kBrickZ == 4, "four 4 x 4 x 4 wave sub-cubes per brick");
 constexpr int kHist = 1024;        // fine bins per LDS window pass
 constexpr int kMaxNB = 8;          // volumes per launch
 
