@@ -190,10 +190,26 @@ def main():
                          f"{nv} evenly spaced voxels over all {prob.K} transducers ({t_a:.1f}s), FP64 surface "
                          f"method; rate = 1/(t_A/pair + t_AT/pair)"}
         from numpy.linalg import norm
+
+        def rl2(a, b):
+            return float(norm(a - b) / norm(b))
+
+        # quadrature rows are also compared with the oracle's own quadrature
+        # (same points: rounding only) on a smaller sample
+        qk, qv = ks[:4], vs[::4]
+        q_ref = None
+        if any(k.startswith("quadrature") for k in results):
+            t = time.perf_counter()
+            q_ref = (O.forward(prob, ksub=qk, mode=O.MODE_POINT, kernel=(h, nf)),
+                     O.adjoint(prob, vsub=qv, mode=O.MODE_POINT, kernel=(h, nf)))
+            log(f"[bench] oracle quadrature sample: {time.perf_counter() - t:.1f}s")
         for key, r in results.items():
-            if key.startswith("closed"):
-                rel[key] = {"forward": float(norm(r["s"][:, ks, :] - s_ref) / norm(s_ref)),
-                            "adjoint": float(norm(r["z"][:, vs] - z_ref) / norm(z_ref))}
+            # against the FP64 closed-form oracle: rounding for the closed form,
+            # method error (plus rounding) for the quadrature
+            rel[key] = {"forward": rl2(r["s"][:, ks, :], s_ref), "adjoint": rl2(r["z"][:, vs], z_ref)}
+            if key.startswith("quadrature") and q_ref is not None:
+                rel[key]["forward_vs_oracle_quadrature"] = rl2(r["s"][:, qk, :], q_ref[0])
+                rel[key]["adjoint_vs_oracle_quadrature"] = rl2(r["z"][:, qv], q_ref[1])
         log(f"[bench] oracle: {rate:.3e} pairs/s on {threads} threads; rel errors {rel}")
 
     value = main_res["pairs_per_s"]

@@ -163,11 +163,13 @@ def apply(op: PatOperator, coef: torch.Tensor) -> torch.Tensor:
 def power_iteration(op: PatOperator, iters: int = 20, seed: int = 7) -> float:
     """Largest eigenvalue of A^T A by power iteration (for a step size)."""
     g = torch.Generator(device="cpu").manual_seed(seed)
-    v = torch.rand(1, op.N, generator=g, dtype=torch.float64).to(op.device, op.dtype)
+    v = torch.rand(1, op.N, generator=g, dtype=torch.float64).to(op.device)
     lam = 0.0
     for _ in range(iters):
+        # norms and the Rayleigh quotient in FP64: the entries of A^T A v are
+        # ~1e-27 for physical units, whose squares underflow FP32
         v = v / torch.linalg.vector_norm(v)
-        w = op.adjoint(op.forward(v))
+        w = op.adjoint(op.forward(v.to(op.dtype))).double()
         lam = float(torch.sum(v * w))
         v = w
     return lam
