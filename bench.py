@@ -24,11 +24,16 @@ sys.path.insert(0, ROOT)
 METRIC = "A+Aᵀ voxel×transducer pairs/s, closed-form FP32 vs quadrature/FP64 at rel err"
 
 # Algorithmic FLOPs per area evaluation (one quadrant of one voxel-transducer
-# pair in one fine bin), counted from the arithmetic of the common path
-# (FMA = 2, add/mul = 1, sqrt/rcp/rsq = 1; Newton refinements included).
+# pair in one fine bin), with the per-pair and per-quadrant setup spread over
+# the evaluations: the operations of the device formulas counted one by one
+# (FMA = 2, add/mul = 1, sqrt/rsq/rcp = 1, library sin/cos/atan at their
+# polynomial length) over a sample of the 128^3 x 256-cylinder workload, where
+# the Carlson loop runs its actual number of steps.
 FLOPS_PER_EVAL = {
-    ("closed", 0): 106.0,   # planar, FP32 cancellation-free form
-    ("closed", 1): 435.0,   # cylinder, FP64 Alg. 4 edge with Legendre addition + Carlson
+    ("closed", 0, "fp32"): 106.0,   # planar, FP32 cancellation-free form (static count of the common path)
+    ("closed", 0, "fp64"): 106.0,
+    ("closed", 1, "fp32"): 327.5,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
+    ("closed", 1, "fp64"): 382.3,   # cylinder, two Newton steps
 }
 # per surface point of the quadrature (FP64 distance + bin test, FP32/FP64 weight)
 FLOPS_PER_POINT = 14.0
@@ -158,7 +163,7 @@ def main():
     fwd_ms, adj_ms = main_res["ms_forward"], main_res["ms_adjoint"]
     dom_ms = max(fwd_ms, adj_ms)
     dom_name = "k_adj_closed" if adj_ms >= fwd_ms else "k_fwd_closed"
-    flops = FLOPS_PER_EVAL[("closed", shape)] * main_res["evals_per_volume"] * B
+    flops = FLOPS_PER_EVAL[("closed", shape, "fp32")] * main_res["evals_per_volume"] * B
     area_dtype = "f64" if shape == 1 else "f32"
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAKS[area_dtype] / 1e12

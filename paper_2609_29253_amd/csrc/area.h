@@ -339,13 +339,45 @@ struct CyEdge {
     double I;
 };
 
+// sin and cos of x in [0, pi/2] (a half angle of the folded interval [0, pi]):
+// Taylor series through x^23 and x^22, whose first omitted terms are below
+// 2e-18 on that range, so no argument reduction is needed
+__device__ __forceinline__ void sincos_quarter(double x, double& s, double& c)
+{
+    const double y = x * x;
+    double ps = -1.0 / 25852016738884976640000.0;              // -1/23!
+    ps = fma(y, ps, 1.0 / 51090942171709440000.0);            // 1/21!
+    ps = fma(y, ps, -1.0 / 121645100408832000.0);             // -1/19!
+    ps = fma(y, ps, 1.0 / 355687428096000.0);                 // 1/17!
+    ps = fma(y, ps, -1.0 / 1307674368000.0);                  // -1/15!
+    ps = fma(y, ps, 1.0 / 6227020800.0);                      // 1/13!
+    ps = fma(y, ps, -1.0 / 39916800.0);                       // -1/11!
+    ps = fma(y, ps, 1.0 / 362880.0);                          // 1/9!
+    ps = fma(y, ps, -1.0 / 5040.0);                           // -1/7!
+    ps = fma(y, ps, 1.0 / 120.0);                             // 1/5!
+    ps = fma(y, ps, -1.0 / 6.0);                              // -1/3!
+    s = fma(x * y, ps, x);
+    double pc = 1.0 / 1124000727777607680000.0;               // 1/22!
+    pc = fma(y, pc, -1.0 / 2432902008176640000.0);            // -1/20!
+    pc = fma(y, pc, 1.0 / 6402373705728000.0);                // 1/18!
+    pc = fma(y, pc, -1.0 / 20922789888000.0);                 // -1/16!
+    pc = fma(y, pc, 1.0 / 87178291200.0);                     // 1/14!
+    pc = fma(y, pc, -1.0 / 479001600.0);                      // -1/12!
+    pc = fma(y, pc, 1.0 / 3628800.0);                         // 1/10!
+    pc = fma(y, pc, -1.0 / 40320.0);                          // -1/8!
+    pc = fma(y, pc, 1.0 / 720.0);                             // 1/6!
+    pc = fma(y, pc, -1.0 / 24.0);                             // -1/4!
+    pc = fma(y, pc, 0.5);
+    c = fma(-y, pc, 1.0);
+}
+
 __device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, double b, double c,
                                          double d, double r0)
 {
     q.a = a; q.b = b; q.c = c; q.d = d;
     double sa, ca, sb, cb;
-    sincos(0.5 * a, &sa, &ca);
-    sincos(0.5 * b, &sb, &cb);
+    sincos_quarter(0.5 * a, sa, ca);
+    sincos_quarter(0.5 * b, sb, cb);
     q.sa = sa; q.ca = ca; q.sb = sb; q.cb = cb;
     double psia = fma(P.mu * sa, sa, P.dm * P.dm);
     double psib = fma(P.mu * sb, sb, P.dm * P.dm);
