@@ -45,9 +45,11 @@ def lib():
         L.or_shell_area.argtypes = [_pd, _pd, _d, _d]
         L.or_pair_areas.restype = _l
         L.or_pair_areas.argtypes = [_pd, _pd, _d, _d, _d, _pl, _pl, _pd, _l]
+        L.or_pair_areas_mode.restype = _l
+        L.or_pair_areas_mode.argtypes = [_pd, _pd, _d, _d, _d, _i, _i, _pl, _pl, _pd, _l]
         L.or_quad_points.restype = None
         L.or_quad_points.argtypes = [_pd, _i, _i, _pd, _pd]
-        common = [_pd, _i, _pl, _pd, _d, _pd, _l, _l, _d, _d, _d, _i, _i, _i, _i, _i]
+        common = [_pd, _i, _pl, _pd, _d, _pd, _l, _l, _d, _d, _d, _i, _i, _i, _i, _i, _i]
         L.or_fcoef.restype = None
         L.or_fcoef.argtypes = common + [_pd, _i, _i, _pd, _pl, _pl]
         L.or_forward.restype = None
@@ -118,6 +120,20 @@ def pair_areas(tr_row, x, c, t0, ufs):
     return l0.value, out[:n].copy()
 
 
+def pair_areas_mode(tr_row, x, c, t0, ufs, mode=0, step=1):
+    """Areas of one pair as a surface method uses them: exact (MODE_SURFACE) or
+    with the trapezoidal I_l (MODE_TRAPEZOID), split from the coarse shells of
+    ``step`` fine bins (Remark 1) when step > 1.  Returns (first bin, areas)."""
+    cap = 1 << 16
+    out = np.zeros(cap)
+    l0, l1 = _l(0), _l(0)
+    n = lib().or_pair_areas_mode(_p(_f64(tr_row)), _p(_f64(x)), c, t0, ufs, int(mode), int(step),
+                                 ctypes.byref(l0), ctypes.byref(l1), _p(out), cap)
+    if n < 0:
+        raise RuntimeError("bin range too long")
+    return l0.value, out[:n].copy()
+
+
 def quad_points(tr_row, n1, n2):
     pts = np.zeros((n1 * n2, 3))
     dA = _d(0)
@@ -127,23 +143,25 @@ def quad_points(tr_row, n1, n2):
 
 MODE_SURFACE = 0
 MODE_POINT = 1
+MODE_TRAPEZOID = 2
 
 
-def _common(prob, h, nf, mode):
+def _common(prob, h, nf, mode, step):
     tr = _f64(prob.tr.packed)
     n = np.ascontiguousarray(prob.grid.n, dtype=np.int64)
     org = _f64(prob.grid.origin)
+    step = int(getattr(prob, "area_step", 1) if step is None else step)
     return (tr, n, org, h), (_p(tr), prob.K, _p(n, _pl), _p(org), prob.grid.spacing, _p(h), nf, len(h),
                              prob.sound_speed, prob.fs, prob.t0, prob.L, prob.U, int(mode),
-                             int(prob.quad_n[0]), int(prob.quad_n[1]))
+                             int(prob.quad_n[0]), int(prob.quad_n[1]), step)
 
 
-def fcoef(prob, k, coef=None, mode=MODE_SURFACE, kernel=None):
+def fcoef(prob, k, coef=None, mode=MODE_SURFACE, kernel=None, step=None):
     """Geometric coefficients f_k (B x M) on bins Mlo..Mhi, returned with Mlo."""
     h, nf = kernel if kernel is not None else kernel_of(prob)
     h = _f64(h)
     coef = _f64(np.atleast_2d(prob.coef if coef is None else coef))
-    keep, args = _common(prob, h, nf, mode)
+    keep, args = _common(prob, h, nf, mode, step)
     Mlo, Mhi = _l(0), _l(0)
     lib().or_fcoef(*args, _p(coef), coef.shape[0], int(k), None, ctypes.byref(Mlo), ctypes.byref(Mhi))
     f = np.zeros((coef.shape[0], Mhi.value - Mlo.value + 1))
@@ -151,19 +169,19 @@ def fcoef(prob, k, coef=None, mode=MODE_SURFACE, kernel=None):
     return f, Mlo.value
 
 
-def forward(prob, coef=None, ksub=None, mode=MODE_SURFACE, kernel=None):
+def forward(prob, coef=None, ksub=None, mode=MODE_SURFACE, kernel=None, step=None):
     """A p0 on the transducers ``ksub`` (default all): array (B, len(ksub), L)."""
     h, nf = kernel if kernel is not None else kernel_of(prob)
     h = _f64(h)
     coef = _f64(np.atleast_2d(prob.coef if coef is None else coef))
     ksub = np.arange(prob.K, dtype=np.int32) if ksub is None else np.ascontiguousarray(ksub, dtype=np.int32)
-    keep, args = _common(prob, h, nf, mode)
+    keep, args = _common(prob, h, nf, mode, step)
     out = np.zeros((coef.shape[0], len(ksub), prob.L))
     lib().or_forward(*args, _p(coef), coef.shape[0], _p(ksub, _pi), len(ksub), _p(out))
     return out
 
 
-def adjoint(prob, y=None, vsub=None, mode=MODE_SURFACE, kernel=None):
+def adjoint(prob, y=None, vsub=None, mode=MODE_SURFACE, kernel=None, step=None):
     """A^T y on the voxels ``vsub`` (default all): array (B, len(vsub))."""
     h, nf = kernel if kernel is not None else kernel_of(prob)
     h = _f64(h)
@@ -171,7 +189,7 @@ def adjoint(prob, y=None, vsub=None, mode=MODE_SURFACE, kernel=None):
     if y.ndim == 2:
         y = y[None]
     vsub = np.arange(prob.N, dtype=np.int64) if vsub is None else np.ascontiguousarray(vsub, dtype=np.int64)
-    keep, args = _common(prob, h, nf, mode)
+    keep, args = _common(prob, h, nf, mode, step)
     out = np.zeros((y.shape[0], len(vsub)))
     lib().or_adjoint(*args, _p(y), y.shape[0], _p(vsub, _pl), len(vsub), _p(out))
     return out

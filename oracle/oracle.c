@@ -19,6 +19,9 @@
  *                          cylinder: Sec. 4.2, Eq. folded_intervals, Eq. cyl_Il
  *                          (Lemma exact_integral, appendix on elliptic integrals)
  *   point coefficients     Alg. 2, Eq. def_f_point, midpoint tensor rule (Prop. 2)
+ *   trapezoidal I_l        Eq. trapezoid_Il (cylinder; the planar I_l stays exact)
+ *   coarse area grid       Remark 1: the area of each shell of step fine bins,
+ *                          split evenly over those bins (step = 1: exact)
  *   adjoint A^T            Alg. 5, 6, 7 (transpose of the downsampling,
  *                          correlation with the reversed kernel, gather)
  *
@@ -53,6 +56,7 @@
 #define OR_CYLINDER 1
 #define OR_MODE_SURFACE 0
 #define OR_MODE_POINT 1
+#define OR_MODE_TRAPEZOID 2
 
 /* ------------------------------------------------------------------------- */
 /* Carlson symmetric elliptic integrals (DLMF 19.36.1 and 19.36.2)            */
@@ -421,7 +425,7 @@ typedef struct { double al, be, I; } otriple;
 
 /* alpha/beta = clamped Phi(v, r) (Eq. alphabeta) and I (Eq. plane_primitive /
    Eq. cyl_Il) for one quadrant at radius r. */
-static otriple quad_edge(const opair* P, const oquad* q, double r)
+static otriple quad_edge(const opair* P, const oquad* q, double r, int trap)
 {
     otriple T;
     double r2 = r * r;
@@ -462,6 +466,14 @@ static otriple quad_edge(const opair* P, const oquad* q, double r)
     }
     double Kc = r2 - dm * dm;   /* 2 R rho + b(r) */
     if (!(T.be > T.al) || !(Kc > 0.0)) { T.I = 0.0; return T; }
+    if (trap) {
+        /* Eq. trapezoid_Il: the level curve u -> Psi(u, r) = sqrt(r^2 - psi(u))
+           replaced by the chord between its end points */
+        double pa_ = sqrt(fmax(0.0, r2 - psi_of(P, T.al)));
+        double pb_ = sqrt(fmax(0.0, r2 - psi_of(P, T.be)));
+        T.I = 0.5 * (T.be - T.al) * (pa_ + pb_);
+        return T;
+    }
     double nu = 4.0 * R * rho / Kc;
     T.I = 2.0 * sqrt(Kc) * (ellip_e_sc(sb, cb, nu) - ellip_e_sc(sa, ca, nu));
     return T;
@@ -469,12 +481,12 @@ static otriple quad_edge(const opair* P, const oquad* q, double r)
 
 /* |D^l| summed over quadrants (Eq. area_D_l_xi, Eq. swept_u) given the triples at
    the previous edge; updates the triples to the new edge (Alg. 4). */
-static double alg4_step(const opair* P, otriple* tri, double r)
+static double alg4_step(const opair* P, otriple* tri, double r, int trap)
 {
     double area = 0.0;
     for (int k = 0; k < P->nq; ++k) {
         const oquad* q = &P->q[k];
-        otriple T = quad_edge(P, q, r);
+        otriple T = quad_edge(P, q, r, trap);
         area += P->J0 * ((T.al - tri[k].al) * q->d + T.I - tri[k].I - (T.be - tri[k].be) * q->c);
         tri[k] = T;
     }
@@ -496,14 +508,14 @@ double or_shell_area(const double* tr, const double* x, double r0, double r1)
     opair P;
     pair_setup(tr, x, &P);
     otriple tri[4];
-    for (int k = 0; k < P.nq; ++k) tri[k] = quad_edge(&P, &P.q[k], r0);
-    return alg4_step(&P, tri, r1);
+    for (int k = 0; k < P.nq; ++k) tri[k] = quad_edge(&P, &P.q[k], r0, 0);
+    return alg4_step(&P, tri, r1, 0);
 }
 
 /* Bin range (Eq. rmin_rmax) and the areas of every bin in it, carrying the
    triples from edge to edge (Alg. 3 + Alg. 4).  Returns the count, or -1. */
-long or_pair_areas(const double* tr, const double* x, double c, double t0, double ufs,
-                   long* lmin, long* lmax, double* out, long cap)
+static long pair_areas(const double* tr, const double* x, double c, double t0, double ufs, int trap,
+                       long* lmin, long* lmax, double* out, long cap)
 {
     opair P;
     pair_setup(tr, x, &P);
@@ -515,8 +527,58 @@ long or_pair_areas(const double* tr, const double* x, double c, double t0, doubl
     if (l1 - l0 + 1 > cap) return -1;
     otriple tri[4];
     alg4_init(&P, tri);
-    for (long l = l0; l <= l1; ++l) out[l - l0] = alg4_step(&P, tri, c * (t0 + l / ufs));
+    for (long l = l0; l <= l1; ++l) out[l - l0] = alg4_step(&P, tri, c * (t0 + l / ufs), trap);
     return l1 - l0 + 1;
+}
+
+long or_pair_areas(const double* tr, const double* x, double c, double t0, double ufs,
+                   long* lmin, long* lmax, double* out, long cap)
+{
+    return pair_areas(tr, x, c, t0, ufs, 0, lmin, lmax, out, cap);
+}
+
+static long floor_div(long a, long b)
+{
+    long q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
+/* Remark 1: the area of each shell of `step` fine bins, shell j holding the bins
+   (j - 1) step + 1 .. j step, split evenly over its bins.  a holds the fine areas
+   of the bins *l0 .. *l0 + cnt - 1; on return out holds the split areas of the
+   bins *l0 .. *l0 + (returned count) - 1, whole shells.  Returns -1 if more than
+   cap bins. */
+static long shell_split(int step, long* l0, long cnt, const double* a, double* out, long cap)
+{
+    if (cnt <= 0) return cnt;
+    long b0 = *l0, b1 = *l0 + cnt - 1;
+    long j0 = -floor_div(-b0, step), j1 = -floor_div(-b1, step);   /* ceil(b / step) */
+    long s0 = (j0 - 1) * step + 1, s1 = j1 * step;
+    if (s1 - s0 + 1 > cap) return -1;
+    for (long j = j0; j <= j1; ++j) {
+        double sum = 0.0;
+        for (long l = (j - 1) * step + 1; l <= j * step; ++l)
+            if (l >= b0 && l <= b1) sum += a[l - b0];
+        for (long l = (j - 1) * step + 1; l <= j * step; ++l) out[l - s0] = sum / step;
+    }
+    *l0 = s0;
+    return s1 - s0 + 1;
+}
+
+/* The areas a surface method uses for one pair: exact (mode 0) or with the
+   trapezoidal I_l (mode 2), on the fine bins (step 1) or split from the shells
+   of the coarse area grid (step > 1). */
+long or_pair_areas_mode(const double* tr, const double* x, double c, double t0, double ufs, int mode,
+                        int step, long* lmin, long* lmax, double* out, long cap)
+{
+    long cnt = pair_areas(tr, x, c, t0, ufs, mode == OR_MODE_TRAPEZOID, lmin, lmax, out, cap);
+    if (cnt <= 0 || step <= 1) return cnt;
+    double* fine = (double*)malloc(sizeof(double) * cnt);
+    memcpy(fine, out, sizeof(double) * cnt);
+    long n = shell_split(step, lmin, cnt, fine, out, cap);
+    free(fine);
+    if (n >= 0) *lmax = *lmin + n - 1;
+    return n;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -566,15 +628,15 @@ typedef struct {
     const double* h;
     long nf, hlen;
     double c, fs, t0;
-    int L, U, mode, q1, q2;
+    int L, U, mode, q1, q2, step;
     long Mlo, Mhi;     /* fine bins that can reach an output sample */
 } oop;
 
 static void op_init(oop* o, const double* tr, int K, const long* n, const double* origin, double w,
                     const double* h, long nf, long hlen, double c, double fs, double t0,
-                    int L, int U, int mode, int q1, int q2)
+                    int L, int U, int mode, int q1, int q2, int step)
 {
-    o->tr = tr; o->K = K;
+    o->tr = tr; o->K = K; o->step = step < 1 ? 1 : step;
     for (int a = 0; a < 3; ++a) { o->n[a] = n[a]; o->origin[a] = origin[a]; }
     o->w = w; o->h = h; o->nf = nf; o->hlen = hlen;
     o->c = c; o->fs = fs; o->t0 = t0; o->L = L; o->U = U; o->mode = mode; o->q1 = q1; o->q2 = q2;
@@ -602,7 +664,7 @@ static void fcoef_range(const oop* o, int k, const double* coef, int B, long N, 
     long cap = 1 << 16;
     double *pts = NULL, dA = 0.0;
     int Q = o->q1 * o->q2;
-    if (o->mode == OR_MODE_SURFACE) tmp = (double*)malloc(sizeof(double) * cap);
+    if (o->mode != OR_MODE_POINT) tmp = (double*)malloc(sizeof(double) * cap);
     else {
         pts = (double*)malloc(sizeof(double) * 3 * Q);
         or_quad_points(tr, o->q1, o->q2, pts, &dA);
@@ -613,9 +675,9 @@ static void fcoef_range(const oop* o, int k, const double* coef, int B, long N, 
         if (!any) continue;
         double x[3];
         voxel_xyz(o, i, x);
-        if (o->mode == OR_MODE_SURFACE) {
+        if (o->mode != OR_MODE_POINT) {
             long l0, l1;
-            long cnt = or_pair_areas(tr, x, o->c, o->t0, ufs, &l0, &l1, tmp, cap);
+            long cnt = or_pair_areas_mode(tr, x, o->c, o->t0, ufs, o->mode, o->step, &l0, &l1, tmp, cap);
             for (long j = 0; j < cnt; ++j) {
                 long l = l0 + j;
                 if (l < o->Mlo || l > o->Mhi) continue;
@@ -690,11 +752,11 @@ static void conv_down(const oop* o, const double* f, double* s)
 /* f-coefficients of one transducer, for tests (B x M, bins Mlo..Mhi) */
 void or_fcoef(const double* tr, int K, const long* n, const double* origin, double w,
               const double* h, long nf, long hlen, double c, double fs, double t0,
-              int L, int U, int mode, int q1, int q2, const double* coef, int B,
+              int L, int U, int mode, int q1, int q2, int step, const double* coef, int B,
               int k, double* f, long* Mlo, long* Mhi)
 {
     oop o;
-    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2);
+    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2, step);
     *Mlo = o.Mlo;
     *Mhi = o.Mhi;
     if (f) fcoef(&o, k, coef, B, n[0] * n[1] * n[2], f, 0);
@@ -703,11 +765,11 @@ void or_fcoef(const double* tr, int K, const long* n, const double* origin, doub
 /* Forward operator on a subset of transducers (Alg. 1).  out is B x nk x L. */
 void or_forward(const double* tr, int K, const long* n, const double* origin, double w,
                 const double* h, long nf, long hlen, double c, double fs, double t0,
-                int L, int U, int mode, int q1, int q2, const double* coef, int B,
+                int L, int U, int mode, int q1, int q2, int step, const double* coef, int B,
                 const int* ksub, int nk, double* out)
 {
     oop o;
-    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2);
+    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2, step);
     long N = n[0] * n[1] * n[2];
     long M = o.Mhi - o.Mlo + 1;
     if (nk >= or_num_threads()) {
@@ -751,11 +813,11 @@ static void adj_prep(const oop* o, const double* yk, double* v)
    y is B x K x L; out is B x nv. */
 void or_adjoint(const double* tr, int K, const long* n, const double* origin, double w,
                 const double* h, long nf, long hlen, double c, double fs, double t0,
-                int L, int U, int mode, int q1, int q2, const double* y, int B,
+                int L, int U, int mode, int q1, int q2, int step, const double* y, int B,
                 const long* vsub, long nv, double* out)
 {
     oop o;
-    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2);
+    op_init(&o, tr, K, n, origin, w, h, nf, hlen, c, fs, t0, L, U, mode, q1, q2, step);
     long M = o.Mhi - o.Mlo + 1;
     double ufs = U * fs;
     double* V = (double*)malloc(sizeof(double) * M * K * B);
@@ -784,9 +846,9 @@ void or_adjoint(const double* tr, int K, const long* n, const double* origin, do
             for (int b = 0; b < B; ++b) z[b] = 0.0;
             for (int k = 0; k < K; ++k) {
                 const double* t = tr + 16 * k;
-                if (mode == OR_MODE_SURFACE) {
+                if (mode != OR_MODE_POINT) {
                     long l0, l1;
-                    long cnt = or_pair_areas(t, x, c, t0, ufs, &l0, &l1, tmp, cap);
+                    long cnt = or_pair_areas_mode(t, x, c, t0, ufs, mode, o.step, &l0, &l1, tmp, cap);
                     for (long j = 0; j < cnt; ++j) {
                         long l = l0 + j;
                         if (l < o.Mlo || l > o.Mhi) continue;

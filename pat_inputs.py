@@ -152,6 +152,7 @@ class Problem:
     coef: Optional[np.ndarray] = None       # (B, N) float64
     y: Optional[np.ndarray] = None          # (B, K, L) float64
     meta: dict = dataclasses.field(default_factory=dict)
+    area_step: int = 1                      # coarse area grid: fine bins per evaluated shell
 
     @property
     def K(self):
