@@ -452,25 +452,28 @@ static otriple quad_edge(const opair* P, const oquad* q, double r, int trap)
     double pa = psi_of(P, q->a), pb = psi_of(P, q->b);
     double sa, ca, sb, cb;       /* sin, cos of alpha/2 and beta/2 */
     double qa = r2 - q->d * q->d, qb = r2 - q->c * q->c;
+    int ia = 0, ib = 0;          /* end point inside (a, b): on the line v = d, resp. v = c */
     if (qa <= pa) { T.al = q->a; sa = sin(0.5 * q->a); ca = cos(0.5 * q->a); }
     else if (qa >= pb) { T.al = q->b; sa = sin(0.5 * q->b); ca = cos(0.5 * q->b); }
     else {
         double h = atan2(sqrt(qa - dm * dm), sqrt(dp * dp - qa));
-        T.al = 2.0 * h; sa = sin(h); ca = cos(h);
+        T.al = 2.0 * h; sa = sin(h); ca = cos(h); ia = 1;
     }
     if (qb <= pa) { T.be = q->a; sb = sin(0.5 * q->a); cb = cos(0.5 * q->a); }
     else if (qb >= pb) { T.be = q->b; sb = sin(0.5 * q->b); cb = cos(0.5 * q->b); }
     else {
         double h = atan2(sqrt(qb - dm * dm), sqrt(dp * dp - qb));
-        T.be = 2.0 * h; sb = sin(h); cb = cos(h);
+        T.be = 2.0 * h; sb = sin(h); cb = cos(h); ib = 1;
     }
     double Kc = r2 - dm * dm;   /* 2 R rho + b(r) */
     if (!(T.be > T.al) || !(Kc > 0.0)) { T.I = 0.0; return T; }
     if (trap) {
         /* Eq. trapezoid_Il: the level curve u -> Psi(u, r) = sqrt(r^2 - psi(u))
-           replaced by the chord between its end points */
-        double pa_ = sqrt(fmax(0.0, r2 - psi_of(P, T.al)));
-        double pb_ = sqrt(fmax(0.0, r2 - psi_of(P, T.be)));
+           replaced by the chord between its end points.  An end point inside
+           (a, b) lies on its line by definition (Eq. alphabeta), so Psi there
+           is that line's v; only a clamped end point needs the square root */
+        double pa_ = ia ? q->d : sqrt(fmax(0.0, r2 - psi_of(P, T.al)));
+        double pb_ = ib ? q->c : sqrt(fmax(0.0, r2 - psi_of(P, T.be)));
         T.I = 0.5 * (T.be - T.al) * (pa_ + pb_);
         return T;
     }
