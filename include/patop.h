@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PATOP_ABI_VERSION 1
+#define PATOP_ABI_VERSION 2
 
 typedef enum {
     PAT_OK = 0,
@@ -58,7 +58,11 @@ typedef enum {
 } pat_status;
 
 enum { PAT_PLANAR = 0, PAT_CYLINDER = 1 };
-enum { PAT_AREA_CLOSED = 0, PAT_AREA_QUADRATURE = 1 };
+/* PAT_AREA_CLOSED: exact shell areas (Alg. 3 with Alg. 4).
+ * PAT_AREA_QUADRATURE: surface points (Alg. 2, Eq. def_f_point).
+ * PAT_AREA_TRAPEZOID: as PAT_AREA_CLOSED, but the cylinder's I_l by the chord of
+ *   the level curve (Eq. trapezoid_Il, no elliptic integral); planar unchanged. */
+enum { PAT_AREA_CLOSED = 0, PAT_AREA_QUADRATURE = 1, PAT_AREA_TRAPEZOID = 2 };
 enum { PAT_FP32 = 0, PAT_FP64 = 1 };
 enum { PAT_PHI_CONE = 0, PAT_PHI_WENDLAND2 = 1 };
 enum { PAT_EIR_GAUSS_COS = 0, PAT_EIR_SAMPLED = 1 };
@@ -115,12 +119,18 @@ typedef struct {
     double t0;             /* recording origin t_0 >= 0, s (Eq. def_operatorS) */
     int32_t L;             /* samples per transducer                   */
     int32_t U;             /* up-sampling factor of the fine grid      */
-    int32_t area_mode;     /* PAT_AREA_CLOSED or PAT_AREA_QUADRATURE   */
+    int32_t area_mode;     /* PAT_AREA_CLOSED, PAT_AREA_QUADRATURE or PAT_AREA_TRAPEZOID */
     int32_t quad_n1;       /* quadrature cells along the first surface coordinate  */
     int32_t quad_n2;       /* quadrature cells along the second surface coordinate */
     int32_t precision;     /* PAT_FP32 or PAT_FP64 (element type of device buffers) */
     int32_t max_batch;     /* workspace is sized for this many volumes (>= 1)      */
     int32_t flags;         /* must be 0                                            */
+    int32_t area_step;     /* coarse area grid of Remark 1: the area of each shell of
+                              area_step fine bins (bins (j-1) area_step + 1 .. j area_step)
+                              is evaluated once and split evenly over its bins;
+                              1 = every fine bin (exact); 1..U for the closed and
+                              trapezoid modes, 1 for quadrature                    */
+    int32_t reserved;      /* must be 0                                            */
 } pat_params;
 
 typedef struct pat_ctx pat_ctx;

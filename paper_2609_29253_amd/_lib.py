@@ -16,7 +16,8 @@ STATUS_NAMES = ["PAT_OK", "PAT_E_ARG", "PAT_E_FRAME", "PAT_E_SHAPE", "PAT_E_SEPA
                 "PAT_E_STATE", "PAT_E_DEVICE", "PAT_E_OOM", "PAT_E_UNSUPPORTED"]
 
 PAT_PLANAR, PAT_CYLINDER = 0, 1
-PAT_AREA_CLOSED, PAT_AREA_QUADRATURE = 0, 1
+PAT_AREA_CLOSED, PAT_AREA_QUADRATURE, PAT_AREA_TRAPEZOID = 0, 1, 2
+ABI_VERSION = 2
 PAT_FP32, PAT_FP64 = 0, 1
 PAT_PHI_CONE, PAT_PHI_WENDLAND2 = 0, 1
 PAT_EIR_GAUSS_COS, PAT_EIR_SAMPLED = 0, 1
@@ -60,7 +61,8 @@ class Params(ctypes.Structure):
     _fields_ = [("sound_speed", ctypes.c_double), ("fs", ctypes.c_double), ("t0", ctypes.c_double),
                 ("L", ctypes.c_int32), ("U", ctypes.c_int32), ("area_mode", ctypes.c_int32),
                 ("quad_n1", ctypes.c_int32), ("quad_n2", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32), ("area_step", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None

@@ -468,8 +468,22 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
 }
 
-// Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I (Eq. cyl_Il)
-template <int NW>
+// asin(u) for 0 <= u <= 0.05: odd Taylor series through u^11 (the first
+// omitted term is < 5e-18 relative)
+__device__ __forceinline__ double asin_small(double u)
+{
+    double y = u * u;
+    double p = 63.0 / 2816;
+    p = fma(y, p, 35.0 / 1152);
+    p = fma(y, p, 5.0 / 112);
+    p = fma(y, p, 3.0 / 40);
+    p = fma(y, p, 1.0 / 6);
+    return fma(u * y, p, u);
+}
+
+// Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I
+// (Eq. cyl_Il; with TRAP the chord of the level curve, Eq. trapezoid_Il)
+template <int NW, bool TRAP = false>
 __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
 {
     double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
@@ -482,6 +496,13 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
     if (!(cr > 0.0)) { E.I = 0.0; return; }
+    if (TRAP) {
+        // (beta - alpha)/2 (Psi(alpha) + Psi(beta)) with Psi = sqrt(K) Delta
+        const double cs = fma(E.cb, E.ca, E.sb * E.sa);   // cos(beta/2 - alpha/2)
+        const double sg = (cr <= 0.05 && cs > 0.0) ? asin_small(cr) : atan2(cr, cs);
+        E.I = K * isK * sg * (E.da + E.db);
+        return;
+    }
     double nu = P.mu * isK * isK;
     double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
     double idn = rcp64(den);
@@ -510,19 +531,6 @@ __device__ __forceinline__ double twice_atan_small(double x)
     return 2.0 * fma(-x * y, p, x);
 }
 
-// asin(u) for 0 <= u <= 0.05: odd Taylor series through u^11 (the first
-// omitted term is < 5e-18 relative)
-__device__ __forceinline__ double asin_small(double u)
-{
-    double y = u * u;
-    double p = 63.0 / 2816;
-    p = fma(y, p, 35.0 / 1152);
-    p = fma(y, p, 5.0 / 112);
-    p = fma(y, p, 3.0 / 40);
-    p = fma(y, p, 1.0 / 6);
-    return fma(u * y, p, u);
-}
-
 // The steps of both end-point angles between consecutive edges, from the sine
 // cr and cosine dt of the half-angle step (negative steps count as zero).  When
 // every active lane of the wave has a small step with dt > 0 the step is
@@ -542,16 +550,16 @@ __device__ __forceinline__ void twice_angles(double cra, double dta, double crb,
     db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2(crb, dtb) : 0.0) : twice_atan_small(xb);
 }
 
-template <int NW, class Sink>
+template <int NW, bool TRAP, class Sink>
 __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, double r0, int wlo, int whi,
                                          double wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
     CyEdge E0, E1;
-    cy_edge<NW>(q, P, r0 + (mb - 1), E0);
+    cy_edge<NW, TRAP>(q, P, r0 + (mb - 1), E0);
     for (int m = mb; m <= me; ++m) {
-        cy_edge<NW>(q, P, r0 + m, E1);
+        cy_edge<NW, TRAP>(q, P, r0 + m, E1);
         double dal, dbe;
         twice_angles(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa),
                      fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb), dal, dbe);

@@ -47,6 +47,12 @@ struct pat_ctx {
 
 namespace {
 
+int64_t floordiv64(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
 const char* kStatusText[] = {"ok",
                              "invalid argument",
                              "transducer frame is not orthonormal",
@@ -208,10 +214,12 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!tr || !grid || !kernel || !prm || K < 1) return fail(c, PAT_E_ARG, "null argument or K < 1");
     const pat_params& p = *prm;
     if (!(p.sound_speed > 0.0) || !(p.fs > 0.0) || !(p.t0 >= 0.0) || !std::isfinite(p.t0) || p.L < 1 || p.U < 1 ||
-        p.max_batch < 1 || p.flags != 0)
+        p.max_batch < 1 || p.flags != 0 || p.reserved != 0)
         return fail(c, PAT_E_ARG, "invalid sampling parameters");
-    if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE)
+    if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE && p.area_mode != PAT_AREA_TRAPEZOID)
         return fail(c, PAT_E_ARG, "invalid area_mode");
+    if (p.area_step < 1 || p.area_step > p.U || (p.area_mode == PAT_AREA_QUADRATURE && p.area_step != 1))
+        return fail(c, PAT_E_ARG, "area_step must be in 1..U (1 for the quadrature)");
     if (p.precision != PAT_FP32 && p.precision != PAT_FP64) return fail(c, PAT_E_ARG, "invalid precision");
     if (p.area_mode == PAT_AREA_QUADRATURE &&
         (p.quad_n1 < 1 || p.quad_n2 < 1 || (int64_t)p.quad_n1 * p.quad_n2 > (1 << 16)))
@@ -233,12 +241,16 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
 
     const double dr = p.sound_speed / (p.U * p.fs);
     const double r0 = p.t0 * p.U * p.fs;
+    const bool surface = p.area_mode != PAT_AREA_QUADRATURE;
+    const int step = p.area_step;
+    const double da = dr * step;          // device length unit: one area shell
+    const double r0a = r0 / step;
     const int64_t nf = kernel->n_first, nl = kernel->n_first + kernel->len - 1;
     const int64_t Mlo = 1 - nl, Mhi = (int64_t)p.U * p.L - nf;
     const int64_t Mcount = Mhi - Mlo + 1;
     if (Mcount < 1 || Mhi > (1 << 30) || Mlo < -(1 << 30)) return fail(c, PAT_E_UNSUPPORTED, "time axis too long");
 
-    // ---- transducer table (dr units)
+    // ---- transducer table (da units)
     std::vector<TrDev> T(K);
     std::vector<int32_t> perm;
     int nplan = 0, ncyl = 0;
@@ -256,15 +268,15 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         std::memset(&d, 0, sizeof d);
         double o[3] = {grid->origin[0] - t.c0[0], grid->origin[1] - t.c0[1], grid->origin[2] - t.c0[2]};
         for (int a = 0; a < 3; ++a) {
-            d.base[a] = dot3(o, ax[a]) / dr;
-            for (int q = 0; q < 3; ++q) d.g[a][q] = grid->spacing * ax[a][q] / dr;
+            d.base[a] = dot3(o, ax[a]) / da;
+            for (int q = 0; q < 3; ++q) d.g[a][q] = grid->spacing * ax[a][q] / da;
         }
         double cen[3], rad;
         bounding_sphere(t, cen, rad);
-        for (int a = 0; a < 3; ++a) d.cen[a] = cen[a] / dr;
-        d.rad = rad / dr;
-        if (t.shape == PAT_PLANAR) { d.p[0] = t.half_w / dr; d.p[1] = t.half_h / dr; }
-        else { d.p[0] = t.radius / dr; d.p[1] = t.theta_max; d.p[2] = t.half_len / dr; }
+        for (int a = 0; a < 3; ++a) d.cen[a] = cen[a] / da;
+        d.rad = rad / da;
+        if (t.shape == PAT_PLANAR) { d.p[0] = t.half_w / da; d.p[1] = t.half_h / da; }
+        else { d.p[0] = t.radius / da; d.p[1] = t.theta_max; d.p[2] = t.half_len / da; }
         d.shape = t.shape;
         double far2 = 0.0;
         for (int a = 0; a < 3; ++a) {
@@ -282,7 +294,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     // ---- per-bin scale (Eq. ui_area: U fs / (c tau_{m-1/2}); point method: U fs)
     std::vector<double> scale(Mcount);
     for (int64_t i = 0; i < Mcount; ++i) {
-        if (p.area_mode == PAT_AREA_CLOSED) {
+        if (surface) {
             double rm = r0 + (double)(Mlo + i) - 0.5;   // c tau_{m-1/2} / dr
             scale[i] = rm > 0.0 ? p.U * p.fs * dr / rm : 0.0;
         } else {
@@ -389,12 +401,15 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     B.K = K;
     for (int a = 0; a < 3; ++a) {
         B.n[a] = grid->n[a];
-        B.origin[a] = grid->origin[a] / dr;
+        B.origin[a] = grid->origin[a] / da;
     }
-    B.w = grid->spacing / dr;
-    B.r0 = r0;
+    B.w = grid->spacing / da;
+    B.r0 = r0a;
     B.Mlo = Mlo;
     B.Mcount = Mcount;
+    B.step = step;
+    B.Jlo = -floordiv64(-Mlo, step);          // ceil(Mlo / step)
+    B.Jhi = -floordiv64(-Mhi, step);
     B.nbx = nbx;
     B.nby = nby;
     B.nbz = nbz;

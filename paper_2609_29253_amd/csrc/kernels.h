@@ -19,7 +19,7 @@ struct LaunchPlan {
     ShapeGroup groups[2];
     int ngroups;
     int nbricks;
-    int mode;               // 0 closed form, 1 quadrature
+    int mode;               // 0 closed form, 1 quadrature, 2 closed form with the trapezoidal cylinder I_l
     bool fp64;
     int U, L;
     int jlo, jcnt;          // polyphase filter G[j], j = jlo .. jlo + jcnt - 1

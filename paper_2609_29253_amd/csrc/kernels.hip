@@ -98,8 +98,8 @@ __device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, 
     double dlo = fmax(sqrt(dd) - T.rad, 0.0), dhi = sqrt(dm) + T.rad;
     int64_t lo = (int64_t)floor(dlo - P.r0);
     int64_t hi = (int64_t)ceil(dhi - P.r0) + 1;
-    lo = max(lo, P.Mlo);
-    hi = min(hi, P.Mlo + P.Mcount - 1);
+    lo = max(lo, P.Jlo);
+    hi = min(hi, P.Jhi);
     wlo = (int)lo;
     whi = (int)hi;
 }
@@ -126,19 +126,29 @@ struct WInt {
     int n;
 };
 
-// intervals [0, A] and [0, B] (A, B >= 0), Eq. uvminmax with the origin inside
+// intervals [0, A] and [0, B] (A, B >= 0), Eq. uvminmax with the origin inside.
+// MERGE: the shared-part form above; else the two intervals as they are, which
+// an approximation that is not additive over sub-intervals (the trapezoidal
+// I_l: the chord of a split arc is not the chord of the arc) must use.
+template <bool MERGE = true>
 __device__ __forceinline__ void split_at_zero(double A, double B, WInt& I)
 {
-    double m = fmin(A, B), M = fmax(A, B);
-    I.lo[0] = 0.0; I.hi[0] = m; I.w[0] = 2.0f;
-    I.lo[1] = m;   I.hi[1] = M; I.w[1] = 1.0f;
+    if (MERGE) {
+        double m = fmin(A, B), M = fmax(A, B);
+        I.lo[0] = 0.0; I.hi[0] = m; I.w[0] = 2.0f;
+        I.lo[1] = m;   I.hi[1] = M; I.w[1] = 1.0f;
+    } else {
+        I.lo[0] = 0.0; I.hi[0] = A; I.w[0] = 1.0f;
+        I.lo[1] = 0.0; I.hi[1] = B; I.w[1] = 1.0f;
+    }
     I.n = 2;
 }
 
 // the reflected intervals of [lo, hi] about 0 (Eq. uvminmax)
+template <bool MERGE = true>
 __device__ __forceinline__ void fold_line(double lo, double hi, WInt& I)
 {
-    if (lo < 0.0 && 0.0 < hi) { split_at_zero(-lo, hi, I); return; }
+    if (lo < 0.0 && 0.0 < hi) { split_at_zero<MERGE>(-lo, hi, I); return; }
     double a = fabs(lo), b = fabs(hi);
     I.lo[0] = fmin(a, b); I.hi[0] = fmax(a, b); I.w[0] = 1.0f;
     I.lo[1] = I.hi[1] = 0.0; I.w[1] = 0.0f;
@@ -192,7 +202,7 @@ __device__ __forceinline__ double wrap_pi(double u)
     return u;
 }
 
-template <int NW>
+template <int NW, bool TRAP>
 struct CylinderPair {
     WInt U, V;
     CyPair P;
@@ -206,21 +216,26 @@ struct CylinderPair {
         P.mu = 4.0 * R * rho;
         P.isq_mu = P.mu > 0.0 ? rsq64(P.mu) : 0.0;
         double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
-        // Eq. folded_intervals
+        // Eq. folded_intervals (merged where the areas are exact, see split_at_zero)
         if (u1 < 0.0 && 0.0 < u2) {
-            split_at_zero(-u1, u2, U);
+            split_at_zero<!TRAP>(-u1, u2, U);
         } else if (u2 < u1) {
             // [u1, pi] and [-u2, pi]
-            double m = fmax(u1, -u2), M = fmin(u1, -u2);
-            U.lo[0] = m; U.hi[0] = M_PI; U.w[0] = 2.0f;
-            U.lo[1] = M; U.hi[1] = m;    U.w[1] = 1.0f;
+            if (TRAP) {
+                U.lo[0] = u1;  U.hi[0] = M_PI; U.w[0] = 1.0f;
+                U.lo[1] = -u2; U.hi[1] = M_PI; U.w[1] = 1.0f;
+            } else {
+                double m = fmax(u1, -u2), M = fmin(u1, -u2);
+                U.lo[0] = m; U.hi[0] = M_PI; U.w[0] = 2.0f;
+                U.lo[1] = M; U.hi[1] = m;    U.w[1] = 1.0f;
+            }
             U.n = 2;
         } else if (0.0 <= u1) {
             U.lo[0] = u1; U.hi[0] = u2; U.w[0] = 1.0f; U.n = 1;
         } else {
             U.lo[0] = -u2; U.hi[0] = -u1; U.w[0] = 1.0f; U.n = 1;
         }
-        fold_line(-Lz - x[2], Lz - x[2], V);
+        fold_line<!TRAP>(-Lz - x[2], Lz - x[2], V);
     }
     // the non-empty quadrants (2 bits each, in sweep order) and their number
     __device__ __forceinline__ int quadrants(int& nq) const
@@ -256,7 +271,7 @@ struct CylinderPair {
             quadrant((list >> (2 * t)) & 3, a, b, c, d, w);
             CyQuad q;
             cy_setup(q, P, a, b, c, d, r0);
-            cy_sweep<NW>(q, P, r0, wlo, whi, w, sink);
+            cy_sweep<NW, TRAP>(q, P, r0, wlo, whi, w, sink);
         }
     }
 };
@@ -267,15 +282,18 @@ struct CylinderPair {
 template <class Real> struct CylNewton { static constexpr int value = 2; };
 template <> struct CylNewton<float> { static constexpr int value = 1; };
 
-template <int SHAPE, class AT, class Real> struct PairOf;
-template <class AT, class Real> struct PairOf<0, AT, Real> { using type = PlanarPair<AT>; };
-template <class AT, class Real> struct PairOf<1, AT, Real> { using type = CylinderPair<CylNewton<Real>::value>; };
+// TRAP: the cylinder's I_l by the trapezoid (Eq. trapezoid_Il); planar I_l is exact either way
+template <int SHAPE, class AT, class Real, bool TRAP> struct PairOf;
+template <class AT, class Real, bool TRAP> struct PairOf<0, AT, Real, TRAP> { using type = PlanarPair<AT>; };
+template <class AT, class Real, bool TRAP> struct PairOf<1, AT, Real, TRAP> {
+    using type = CylinderPair<CylNewton<Real>::value, TRAP>;
+};
 
 // ---------------------------------------------------------------------------
 // forward, closed-form areas
 // ---------------------------------------------------------------------------
 
-template <int SHAPE, class AT, int NB, class Real>
+template <int SHAPE, class AT, int NB, class Real, bool TRAP>
 __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
@@ -306,7 +324,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
             if (nz) {
                 double x[3];
                 frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT, Real>::type pair;
+                typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
                 pair.setup(T, x, P.r0);
                 auto sink = [&](int m, auto area) {
 #pragma unroll
@@ -315,13 +333,20 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
                 pair.sweep(plo, phi, sink, P.r0);
             }
             __syncthreads();
-            const int64_t fo = (plo - P.Mlo);
-            for (int i = threadIdx.x; i < wn; i += kThreads)
+            // shell j holds the fine bins (j - 1) step + 1 .. j step; its area, in
+            // units of (step dr)^2, is split evenly over them (Remark 1): step^2 / step
+            const int S = P.step;
+            const int64_t Mhi = P.Mlo + P.Mcount - 1;
+            for (int i = threadIdx.x; i < wn * S; i += kThreads) {
+                const int jj = i / S;
+                const int64_t m = (int64_t)(plo + jj - 1) * S + 1 + (i - jj * S);
+                if (m < P.Mlo || m > Mhi) continue;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    double v = hist[b * kHist + i];
-                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + fo + i], v);
+                    double v = hist[b * kHist + jj];
+                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + (m - P.Mlo)], v * S);
                 }
+            }
             __syncthreads();
         }
     }
@@ -331,7 +356,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
 // adjoint, closed-form areas
 // ---------------------------------------------------------------------------
 
-template <int SHAPE, class AT, int NB, class Real>
+template <int SHAPE, class AT, int NB, class Real, bool TRAP>
 __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Real* __restrict__ W,
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
@@ -353,15 +378,25 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
             const int phi = min(whi, plo + kHist - 1);
             const int wn = phi - plo + 1;
             __syncthreads();
-            const int64_t fo = (plo - P.Mlo);
+            // transpose of the even split: each shell gathers its fine bins (Remark 1)
+            const int S = P.step;
+            const int64_t Mhi = P.Mlo + P.Mcount - 1;
             for (int i = threadIdx.x; i < wn; i += kThreads)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) Ws[b * kHist + i] = W[((int64_t)b * P.K + k) * P.Mcount + fo + i];
+                for (int b = 0; b < NB; ++b) {
+                    const Real* Wk = W + ((int64_t)b * P.K + k) * P.Mcount;
+                    double acc = 0.0;
+                    for (int t = 0; t < S; ++t) {
+                        const int64_t m = (int64_t)(plo + i - 1) * S + 1 + t;
+                        if (m >= P.Mlo && m <= Mhi) acc += (double)Wk[m - P.Mlo];
+                    }
+                    Ws[b * kHist + i] = (Real)(acc * S);
+                }
             __syncthreads();
             if (Bk.valid) {
                 double x[3];
                 frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT, Real>::type pair;
+                typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
                 pair.setup(T, x, P.r0);
                 AT part[NB];
 #pragma unroll
@@ -548,10 +583,10 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
             if (quad) { evals += P.Q; pairs += 1; continue; }
             double x[3];
             frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-            const int lo = (int)P.Mlo, hi = (int)(P.Mlo + P.Mcount - 1);
+            const int lo = (int)P.Jlo, hi = (int)P.Jhi;
             int nb = 0;
             auto sink = [&](int, auto) { ++nb; };
-            typename PairOf<SHAPE, double, double>::type pair;
+            typename PairOf<SHAPE, double, double, false>::type pair;
             pair.setup(T, x, P.r0);
             pair.sweep(lo, hi, sink, P.r0);
             evals += nb;
@@ -618,29 +653,29 @@ __global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ sc
 
 namespace {
 
-template <int SHAPE, class AT, class Real>
+template <int SHAPE, class AT, class Real, bool TRAP>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
     size_t sh = (size_t)nb * kHist * sizeof(double);
     switch (nb) {
-    case 1: k_fwd_closed<SHAPE, AT, 1, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 2: k_fwd_closed<SHAPE, AT, 2, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 4: k_fwd_closed<SHAPE, AT, 4, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    default: k_fwd_closed<SHAPE, AT, 8, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 1: k_fwd_closed<SHAPE, AT, 1, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 2: k_fwd_closed<SHAPE, AT, 2, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 4: k_fwd_closed<SHAPE, AT, 4, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    default: k_fwd_closed<SHAPE, AT, 8, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     }
     return hipGetLastError();
 }
 
-template <int SHAPE, class AT, class Real>
+template <int SHAPE, class AT, class Real, bool TRAP>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
     size_t sh = (size_t)nb * kHist * sizeof(Real);
     switch (nb) {
-    case 1: k_adj_closed<SHAPE, AT, 1, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 2: k_adj_closed<SHAPE, AT, 2, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 4: k_adj_closed<SHAPE, AT, 4, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    default: k_adj_closed<SHAPE, AT, 8, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 1: k_adj_closed<SHAPE, AT, 1, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_closed<SHAPE, AT, 2, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_closed<SHAPE, AT, 4, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_closed<SHAPE, AT, 8, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     }
     return hipGetLastError();
 }
@@ -703,8 +738,9 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
             const Real* cb = coef + (int64_t)b0 * P.N;
             double* fb = L.f + (int64_t)b0 * P.K * P.Mcount;
             if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
-            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real>(nb, grid, P, cb, fb, s);
-            else e = fwd_closed_nb<1, double, Real>(nb, grid, P, cb, fb, s);
+            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, false>(nb, grid, P, cb, fb, s);
+            else if (L.mode == 2) e = fwd_closed_nb<1, double, Real, true>(nb, grid, P, cb, fb, s);
+            else e = fwd_closed_nb<1, double, Real, false>(nb, grid, P, cb, fb, s);
             if (e != hipSuccess) return e;
         }
         b0 += nb;
@@ -744,8 +780,9 @@ hipError_t adjoint_t(const LaunchPlan& L, const Real* sig, Real* coef, int B, hi
             Real* ob = coef + (int64_t)b0 * P.N;
             double* zb = L.z64 + (int64_t)b0 * P.N;
             if (L.mode == 1) e = adj_quad_nb<Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
-            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
-            else e = adj_closed_nb<1, double, Real>(nb, grid, P, Wb, ob, zb, direct, s);
+            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real, false>(nb, grid, P, Wb, ob, zb, direct, s);
+            else if (L.mode == 2) e = adj_closed_nb<1, double, Real, true>(nb, grid, P, Wb, ob, zb, direct, s);
+            else e = adj_closed_nb<1, double, Real, false>(nb, grid, P, Wb, ob, zb, direct, s);
             if (e != hipSuccess) return e;
         }
         b0 += nb;
@@ -765,8 +802,8 @@ hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_
         KParams P = L.base;
         P.kperm = L.groups[g].kperm;
         P.nk = L.groups[g].nk;
-        if (L.groups[g].shape == 0) k_count<0><<<L.nbricks, kThreads, 0, s>>>(P, L.mode, out);
-        else k_count<1><<<L.nbricks, kThreads, 0, s>>>(P, L.mode, out);
+        if (L.groups[g].shape == 0) k_count<0><<<L.nbricks, kThreads, 0, s>>>(P, L.mode == 1, out);
+        else k_count<1><<<L.nbricks, kThreads, 0, s>>>(P, L.mode == 1, out);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

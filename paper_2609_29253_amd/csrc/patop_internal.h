@@ -1,9 +1,11 @@
 // Internal types shared by the host side (host.hip) and the device kernels
 // (kernels.hip) of the patop library.  Not part of the ABI.
 //
-// Every length on the device is expressed in units of the fine radial step
-// dr = c / (U fs): bin m of the fine time grid (the paper's [tau_{m-1}, tau_m))
-// is then the radial interval [r0 + m - 1, r0 + m) with r0 = c t0 / dr.
+// Every length on the device is expressed in units of the area step
+// da = step * dr, dr = c / (U fs) the fine radial step: area shell j (fine bins
+// (j - 1) step + 1 .. j step of the paper's [tau_{m-1}, tau_m)) is then the
+// radial interval [r0 + j - 1, r0 + j) with r0 = c t0 / da.  With step = 1 (and
+// always for the quadrature) shells are the fine bins.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +45,8 @@ struct KParams {
     double w;               // voxel spacing
     double r0;              // c t0 / dr
     int64_t Mlo, Mcount;    // kept fine bins [Mlo, Mlo + Mcount)
+    int32_t step;           // fine bins per area shell (coarse area grid; 1 = exact)
+    int64_t Jlo, Jhi;       // shells that hold a kept fine bin (= Mlo, Mlo + Mcount - 1 when step = 1)
     int32_t nbx, nby, nbz;  // bricks per axis
     int32_t B;              // volumes in this launch (<= kMaxNB)
     int64_t N;

@@ -57,7 +57,7 @@ class PatOperator:
 
     def __init__(self, packed, n, origin, spacing, h, n_first, kappa, sound_speed, fs, t0, L_, U=1,
                  mode: str = "closed", quad_n: Sequence[int] = (16, 16), precision: str = "fp32",
-                 max_batch: int = 1, device: int = 0):
+                 max_batch: int = 1, device: int = 0, area_step: int = 1):
         self.K = len(packed)
         self.n = tuple(int(v) for v in n)
         self.N = self.n[0] * self.n[1] * self.n[2]
@@ -76,7 +76,12 @@ class PatOperator:
         p = L.Params()
         p.sound_speed, p.fs, p.t0 = float(sound_speed), float(fs), float(t0)
         p.L, p.U = self.L, int(U)
-        p.area_mode = L.PAT_AREA_CLOSED if mode == "closed" else L.PAT_AREA_QUADRATURE
+        modes = {"closed": L.PAT_AREA_CLOSED, "quadrature": L.PAT_AREA_QUADRATURE, "trapezoid": L.PAT_AREA_TRAPEZOID}
+        if mode not in modes:
+            raise ValueError(f"mode must be one of {sorted(modes)}")
+        p.area_mode = modes[mode]
+        p.area_step = int(area_step)
+        p.reserved = 0
         p.quad_n1, p.quad_n2 = int(quad_n[0]), int(quad_n[1])
         p.precision = L.PAT_FP32 if precision == "fp32" else L.PAT_FP64
         p.max_batch = self.max_batch
@@ -85,12 +90,14 @@ class PatOperator:
         L.check(st, self._ctx)
 
     @classmethod
-    def from_problem(cls, prob, mode="closed", precision="fp32", max_batch=None, device=0, kernel=None):
+    def from_problem(cls, prob, mode="closed", precision="fp32", max_batch=None, device=0, kernel=None,
+                     area_step=None):
         h, nf = kernel if kernel is not None else build_kernel(prob.phi_type, prob.kappa, prob.eir,
                                                                prob.sound_speed, prob.fs, prob.U)
         B = max_batch if max_batch is not None else (prob.coef.shape[0] if prob.coef is not None else 1)
         return cls(prob.tr.packed, prob.grid.n, prob.grid.origin, prob.grid.spacing, h, nf, prob.kappa,
-                   prob.sound_speed, prob.fs, prob.t0, prob.L, prob.U, mode, prob.quad_n, precision, B, device)
+                   prob.sound_speed, prob.fs, prob.t0, prob.L, prob.U, mode, prob.quad_n, precision, B, device,
+                   getattr(prob, "area_step", 1) if area_step is None else area_step)
 
     def query(self, what: int) -> float:
         out = ctypes.c_double(0.0)

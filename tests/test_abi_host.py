@@ -103,5 +103,5 @@ def test_forward_without_geometry_is_a_state_error():
     from paper_2609_29253_amd import _lib
     L = _lib.lib()
     out = ctypes.c_double(0)
-    assert L.pat_query(None, 6, ctypes.byref(out)) == 0 and out.value == 1
+    assert L.pat_query(None, 6, ctypes.byref(out)) == 0 and out.value == _lib.ABI_VERSION
     assert L.pat_forward(None, None, None, 1, None) == 1
