@@ -84,6 +84,78 @@ def time_op(op, coef, y, steps, warmup, torch):
     return wall, f, a
 
 
+def run_next(args, prob, kern, B, pairs, torch, dev, log):
+    """Approximate variants: time per A + A^T and rel L2 error against the
+    oracle's exact method (method error) and its own version of the variant
+    (rounding), on bounded samples."""
+    import numpy as np
+    import oracle as O
+    import pat_inputs as P
+    from paper_2609_29253_amd.operator import PatOperator, build_kernel
+
+    def rl2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def timed(p, kern_, mode, step, steps=2):
+        if mode == "quadrature":
+            step = 1
+        op = PatOperator.from_problem(p, mode=mode, precision="fp32", max_batch=B, kernel=kern_, area_step=step)
+        coef = torch.tensor(p.coef, dtype=torch.float32, device=dev)
+        y = torch.tensor(p.y, dtype=torch.float32, device=dev)
+        wall, f_ms, a_ms = time_op(op, coef, y, steps, 1, torch)
+        evals = op.query(7)
+        s = op.forward(coef).double().cpu().numpy()
+        z = op.adjoint(y).double().cpu().numpy()
+        op.close()
+        return wall, f_ms, a_ms, evals, s, z
+
+    rows = {}
+    ks = np.array([0, 131], dtype=np.int32)
+    vs = np.linspace(0, prob.N - 1, 512).astype(np.int64)
+    h, nf = O.kernel_of(prob)
+    shape = 1 if 1 in set(int(v) for v in prob.tr.packed[:, 0]) else 0
+    ex = (O.forward(prob, ksub=ks, kernel=(h, nf)), O.adjoint(prob, vsub=vs, kernel=(h, nf)))
+    if shape == 1:
+        wall, f_ms, a_ms, ev, s, z = timed(prob, kern, "trapezoid", 1, max(1, min(3, args.steps)))
+        tz = (O.forward(prob, ksub=ks, mode=O.MODE_TRAPEZOID, kernel=(h, nf)),
+              O.adjoint(prob, vsub=vs, mode=O.MODE_TRAPEZOID, kernel=(h, nf)))
+        rows["trapezoid_fp32"] = {
+            "workload": prob.name, "ms_per_step": round(wall, 3), "ms_forward": round(f_ms, 3),
+            "ms_adjoint": round(a_ms, 3), "pairs_per_s": pairs / (wall * 1e-3), "area_evaluations": ev,
+            "rel_err_vs_exact_oracle": {"forward": rl2(s[:, ks], ex[0]), "adjoint": rl2(z[:, vs], ex[1])},
+            "rel_err_vs_oracle_trapezoid": {"forward": rl2(s[:, ks], tz[0]), "adjoint": rl2(z[:, vs], tz[1])}}
+        log(f"[bench] next trapezoid: {rows['trapezoid_fp32']}")
+    # the quadrature refined: error against the exact method and cost as Q grows
+    q0 = tuple(prob.quad_n)
+    for qn in (32, 64):
+        prob.quad_n = (qn, qn)
+        wall, f_ms, a_ms, ev, s, z = timed(prob, kern, "quadrature", 1, 1)
+        rows[f"quadrature_{qn}x{qn}_fp32"] = {
+            "workload": prob.name, "ms_per_step": round(wall, 3), "pairs_per_s": pairs / (wall * 1e-3),
+            "rel_err_vs_exact_oracle": {"forward": rl2(s[:, ks], ex[0]), "adjoint": rl2(z[:, vs], ex[1])}}
+        log(f"[bench] next quadrature {qn}x{qn}: {rows[f'quadrature_{qn}x{qn}_fp32']}")
+    prob.quad_n = q0
+    # coarse area grid (Remark 1) at U = 4: every fine bin vs one area per native sample
+    p4 = P.config2(U=4)
+    k4 = build_kernel(p4.phi_type, p4.kappa, p4.eir, p4.sound_speed, p4.fs, p4.U)
+    h4, nf4 = O.kernel_of(p4)
+    ex4 = (O.forward(p4, ksub=ks, kernel=(h4, nf4)), O.adjoint(p4, vsub=vs, kernel=(h4, nf4)))
+    pairs4 = float(p4.coef.shape[0]) * p4.N * p4.K
+    for step in (1, 2, 4):
+        wall, f_ms, a_ms, ev, s, z = timed(p4, k4, "closed", step, 1)
+        row = {"workload": p4.name, "U": 4, "area_step": step, "ms_per_step": round(wall, 3),
+               "ms_forward": round(f_ms, 3), "ms_adjoint": round(a_ms, 3), "pairs_per_s": pairs4 / (wall * 1e-3),
+               "area_evaluations": ev,
+               "rel_err_vs_exact_oracle": {"forward": rl2(s[:, ks], ex4[0]), "adjoint": rl2(z[:, vs], ex4[1])}}
+        if step > 1:
+            cg = (O.forward(p4, ksub=ks, kernel=(h4, nf4), step=step),
+                  O.adjoint(p4, vsub=vs, kernel=(h4, nf4), step=step))
+            row["rel_err_vs_oracle_same_step"] = {"forward": rl2(s[:, ks], cg[0]), "adjoint": rl2(z[:, vs], cg[1])}
+        rows[f"coarse_U4_step{step}_fp32"] = row
+        log(f"[bench] next coarse grid: {row}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +168,9 @@ def main():
                     help="copy a 256 MiB device buffer first (reference kernel for HBM counters)")
     ap.add_argument("--profile-only", action="store_true",
                     help="one forward and one adjoint of the closed FP32 variant, nothing else")
+    ap.add_argument("--next", action="store_true",
+                    help="also time the approximate variants (trapezoidal cylinder I_l on the workload; the "
+                         "coarse area grid on the 128^3 cylinder workload at U = 4) with their errors")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator is built and timed on a single MI355X; "
@@ -217,6 +292,8 @@ def main():
                 rel[key]["adjoint_vs_oracle_quadrature"] = rl2(r["z"][:, qv], q_ref[1])
         log(f"[bench] oracle: {rate:.3e} pairs/s on {threads} threads; rel errors {rel}")
 
+    next_rows = run_next(args, prob, kern, B, pairs, torch, dev, log) if args.next else None
+
     value = main_res["pairs_per_s"]
     variants = {k: {"ms_per_step": round(v["ms_per_step"], 3), "pairs_per_s": v["pairs_per_s"],
                     "speedup_of_closed_fp32": round(v["ms_per_step"] / main_res["ms_per_step"], 3)}
@@ -242,6 +319,8 @@ def main():
         "variants": variants,
         "rel_err_vs_oracle": rel,
     }
+    if next_rows is not None:
+        line["next_rows"] = next_rows
     print(json.dumps(line), flush=True)
 
 

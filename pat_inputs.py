@@ -396,15 +396,17 @@ def config1(U: int = 1) -> Problem:
     return _finish("cfg1_planar64_32c", tr, grid, 40e6, 512, ball_uniform(grid, 1.2e-3, 0), 1, U=U)
 
 
-def config2(n: int = 128) -> Problem:
+def config2(n: int = 128, U: int = 1) -> Problem:
     """128^3 grid (0.1 mm), 256 cylinders (6 mm curved x 3 mm straight,
     R = 25 mm) on a 180-degree arc of radius 40 mm, 16 elements x 16 rotations;
-    fs 50 MHz, L 2048; 200 Gaussian blobs + 16 polylines (seed 0)."""
+    fs 50 MHz, L 2048; 200 Gaussian blobs + 16 polylines (seed 0); fine grid
+    U (1 for the headline, 4 for the coarse-area-grid comparison)."""
     grid = Grid.centred(n, 0.1e-3)
     tr = arc_cylinder_array(16, 16, 40e-3, 25e-3, 6e-3, 3e-3)
     rng = np.random.default_rng(0)
     coef = blobs(grid, rng, 200) + polylines(grid, rng, 16)
-    return _finish("cfg2_cyl256_128c", tr, grid, 50e6, 2048, coef, 1)
+    name = "cfg2_cyl256_128c" if U == 1 else f"cfg2_cyl256_128c_U{U}"
+    return _finish(name, tr, grid, 50e6, 2048, coef, 1, U=U)
 
 
 def config3(n: int = 256) -> Problem:
