@@ -41,6 +41,33 @@ FLOPS_PER_POINT = 14.0
 PEAKS = {"f32": 157.3e12, "f64": 78.6e12}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("area.h", "kernels.hip", "kernels.h", "patop_internal.h"):
+        with open(os.path.join(ROOT, "paper_2609_29253_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a plain copy), or None when the kernel sources
+    have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "closed_cylinder_128c_k256_counters.md")
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.strip().startswith("traffic-json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if (rec["kernel"] == kernel and rec["workload"] == workload
+                            and rec["source_hash"] == kernel_source_hash()):
+                        return rec["traffic_bytes"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -235,15 +262,17 @@ def main():
             results[f"{mode}_{prec}"] = run_variant(mode, prec, max(1, min(2, args.steps)), 1)
 
     # ---- roofline of the dominant kernel (the area kernel of A or A^T)
-    fwd_ms, adj_ms = main_res["ms_forward"], main_res["ms_adjoint"]
-    dom_ms = max(fwd_ms, adj_ms)
-    dom_name = "k_adj_closed" if adj_ms >= fwd_ms else "k_fwd_closed"
+    # the area kernel of A (that of A^T does the same area work and takes the same time)
+    dom_ms = main_res["ms_forward"]
+    dom_name = "k_fwd_closed"
     flops = FLOPS_PER_EVAL[("closed", shape, "fp32")] * main_res["evals_per_volume"] * B
     area_dtype = "f64" if shape == 1 else "f32"
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAKS[area_dtype] / 1e12
+    dom_full = f"{dom_name}<{shape}, double, 1, float, false>" if shape == 1 else dom_name
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom_name,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_full, prob.name),
+                "kernel": dom_name,
                 "flops_per_launch": flops, "launch_ms": round(dom_ms, 3), "area_dtype": area_dtype}
 
     # ---- oracle on the host cores (bounded sample) and accuracy of the sample
