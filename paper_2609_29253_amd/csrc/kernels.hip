@@ -159,6 +159,7 @@ template <class AT>
 struct PlanarPair {
     WInt U, V;
     double z2;
+    __device__ __forceinline__ void bind(double*) {}
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
         double L1 = T.p[0], L2 = T.p[1];
@@ -202,12 +203,21 @@ __device__ __forceinline__ double wrap_pi(double u)
     return u;
 }
 
+// The interval ends of the folded quadrants live in LDS (one column per thread,
+// kBoxSlots doubles), read back per quadrant: kept in registers they would be
+// live through every sweep and pushed to scratch memory at three waves per SIMD.
+constexpr int kBoxSlots = 8;
+
 template <int NW, bool TRAP>
 struct CylinderPair {
-    WInt U, V;
     CyPair P;
+    double* box;             // this thread's column of the LDS box table
+    int list, nq;            // non-empty quadrants (2 bits each, in sweep order) and their number
+    int wbits;               // quadrant weights: bits 0/1 the U intervals, 2/3 the V intervals (set = 2)
+    __device__ __forceinline__ void bind(double* table) { box = table + threadIdx.x; }
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
+        WInt U, V;
         double R = T.p[0], th = T.p[1], Lz = T.p[2];
         double rho = sqrt64(x[0] * x[0] + x[1] * x[1]);
         double thi = (rho > 0.0) ? atan2(x[1], x[0]) : 0.0;
@@ -236,11 +246,7 @@ struct CylinderPair {
             U.lo[0] = -u2; U.hi[0] = -u1; U.w[0] = 1.0f; U.n = 1;
         }
         fold_line<!TRAP>(-Lz - x[2], Lz - x[2], V);
-    }
-    // the non-empty quadrants (2 bits each, in sweep order) and their number
-    __device__ __forceinline__ int quadrants(int& nq) const
-    {
-        int list = 0;
+        list = 0;
         nq = 0;
 #pragma unroll
         for (int qi = 0; qi < 4; ++qi) {
@@ -249,22 +255,25 @@ struct CylinderPair {
                             (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
             if (ok) { list |= qi << (2 * nq); ++nq; }
         }
-        return list;
+        wbits = (U.w[0] > 1.5f ? 1 : 0) | (U.w[1] > 1.5f ? 2 : 0) | (V.w[0] > 1.5f ? 4 : 0) |
+                (V.w[1] > 1.5f ? 8 : 0);
+        box[0 * kThreads] = U.lo[0]; box[1 * kThreads] = U.hi[0];
+        box[2 * kThreads] = U.lo[1]; box[3 * kThreads] = U.hi[1];
+        box[4 * kThreads] = V.lo[0]; box[5 * kThreads] = V.hi[0];
+        box[6 * kThreads] = V.lo[1]; box[7 * kThreads] = V.hi[1];
     }
     __device__ __forceinline__ void quadrant(int qi, double& a, double& b, double& c, double& d, double& w) const
     {
         const int i = qi >> 1, j = qi & 1;
-        a = i ? U.lo[1] : U.lo[0]; b = i ? U.hi[1] : U.hi[0];
-        c = j ? V.lo[1] : V.lo[0]; d = j ? V.hi[1] : V.hi[0];
-        w = (double)((i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]));
+        a = box[(2 * i) * kThreads]; b = box[(2 * i + 1) * kThreads];
+        c = box[(4 + 2 * j) * kThreads]; d = box[(5 + 2 * j) * kThreads];
+        w = (double)((1 + ((wbits >> i) & 1)) * (1 + ((wbits >> (2 + j)) & 1)));
     }
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
         // the lane's non-empty quadrants first, so lanes step through their k-th
         // quadrant together
-        int nq;
-        const int list = quadrants(nq);
 #pragma unroll 1
         for (int t = 0; t < nq; ++t) {
             double a, b, c, d, w;
@@ -298,6 +307,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
                                                           double* __restrict__ f)
 {
     extern __shared__ double hist[];   // [NB][kHist]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     Brick Bk;
     brick_setup(P, Bk);
     double p0[NB];
@@ -311,9 +321,18 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
     const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
-        const TrDev T = P.tr[k];
         int wlo, whi;
-        brick_window(P, Bk, T, wlo, whi);
+        // the pair's geometry once per transducer; the transducer record is not
+        // needed afterwards
+        typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
+        pair.bind(box);
+        {
+            const TrDev T = P.tr[k];
+            brick_window(P, Bk, T, wlo, whi);
+            double x[3];
+            frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+            pair.setup(T, x, P.r0);
+        }
         for (int plo = wlo; plo <= whi; plo += kHist) {
             const int phi = min(whi, plo + kHist - 1);
             const int wn = phi - plo + 1;
@@ -322,10 +341,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
                 for (int b = 0; b < NB; ++b) hist[b * kHist + i] = 0.0;
             __syncthreads();
             if (nz) {
-                double x[3];
-                frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
-                pair.setup(T, x, P.r0);
                 auto sink = [&](int m, auto area) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (m - plo)], p0[b] * (double)area);
@@ -363,6 +378,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
 {
     extern __shared__ double smem_d[];
     Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][kHist]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     Brick Bk;
     brick_setup(P, Bk);
     double acc[NB];
@@ -371,9 +387,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
     const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
-        const TrDev T = P.tr[k];
         int wlo, whi;
-        brick_window(P, Bk, T, wlo, whi);
+        typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
+        pair.bind(box);
+        {
+            const TrDev T = P.tr[k];
+            brick_window(P, Bk, T, wlo, whi);
+            double x[3];
+            frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+            pair.setup(T, x, P.r0);
+        }
         for (int plo = wlo; plo <= whi; plo += kHist) {
             const int phi = min(whi, plo + kHist - 1);
             const int wn = phi - plo + 1;
@@ -394,10 +417,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
                 }
             __syncthreads();
             if (Bk.valid) {
-                double x[3];
-                frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-                typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
-                pair.setup(T, x, P.r0);
                 AT part[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) part[b] = AT(0);
@@ -572,6 +591,7 @@ template <int SHAPE>
 __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigned long long* __restrict__ out)
 {
     __shared__ unsigned long long red[2];
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     if (threadIdx.x < 2) red[threadIdx.x] = 0;
     __syncthreads();
     Brick Bk;
@@ -587,6 +607,7 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
             int nb = 0;
             auto sink = [&](int, auto) { ++nb; };
             typename PairOf<SHAPE, double, double, false>::type pair;
+            pair.bind(box);
             pair.setup(T, x, P.r0);
             pair.sweep(lo, hi, sink, P.r0);
             evals += nb;

@@ -10,7 +10,10 @@ relative rounding per bin in the cylinder (differences of nearly equal
 elliptic integrals), and the zero-mean system kernel amplifies relative errors
 of the fine-bin coefficients by 20-300 (the ratio |h| |f| / |h * f|).
 The dot test is normalised by |A p| |y| (y is white noise, so <A p, y> itself
-is ~sqrt(K L) times smaller than that bound).
+is ~sqrt(K L) times smaller than that bound).  A and A^T sum the same FP64
+products p_i |M_ik^m| W_k[m] in different orders (FP64 atomics in A, so the
+order also varies from run to run); the sums cancel by the same 20-300 factor
+as above, so the FP64 gap sits at ~1e-13 and the bar is 1e-12 (FP32: 1e-6).
 """
 import numpy as np
 import pytest
@@ -74,4 +77,4 @@ def test_fullsize_sampled_parity(gpu, name, ks, prec):
     lhs, rhs = float(np.sum(s * p.y)), float(np.sum(z * p.coef))
     gap = abs(lhs - rhs) / (np.linalg.norm(s) * np.linalg.norm(p.y))
     print(f"[{name} {prec}] <Ap,y> = {lhs:.10e}, <p,A^T y> = {rhs:.10e}, normalised gap {gap:.3e}", flush=True)
-    assert gap < (1e-6 if prec == "fp32" else 1e-13)
+    assert gap < (1e-6 if prec == "fp32" else 1e-12)
