@@ -56,6 +56,12 @@ def lib():
         L.or_forward.argtypes = common + [_pd, _i, _pi, _i, _pd]
         L.or_adjoint.restype = None
         L.or_adjoint.argtypes = common + [_pd, _i, _pl, _l, _pd]
+        L.or_lut_e.restype = _d
+        L.or_lut_e.argtypes = [_d, _d]
+        L.or_lut_entry.restype = None
+        L.or_lut_entry.argtypes = [_i, _i, _pd, _pd, _pd, _pd]
+        L.or_lut_set_size.restype = None
+        L.or_lut_set_size.argtypes = [_i]
         L.or_num_threads.restype = _i
         L.or_set_threads.argtypes = [_i]
         _lib = L
@@ -121,9 +127,10 @@ def pair_areas(tr_row, x, c, t0, ufs):
 
 
 def pair_areas_mode(tr_row, x, c, t0, ufs, mode=0, step=1):
-    """Areas of one pair as a surface method uses them: exact (MODE_SURFACE) or
-    with the trapezoidal I_l (MODE_TRAPEZOID), split from the coarse shells of
-    ``step`` fine bins (Remark 1) when step > 1.  Returns (first bin, areas)."""
+    """Areas of one pair as a surface method uses them: exact (MODE_SURFACE),
+    with the trapezoidal I_l (MODE_TRAPEZOID) or the lookup-table I_l
+    (MODE_LUT), split from the coarse shells of ``step`` fine bins (Remark 1)
+    when step > 1.  Returns (first bin, areas)."""
     cap = 1 << 16
     out = np.zeros(cap)
     l0, l1 = _l(0), _l(0)
@@ -144,6 +151,26 @@ def quad_points(tr_row, n1, n2):
 MODE_SURFACE = 0
 MODE_POINT = 1
 MODE_TRAPEZOID = 2
+MODE_LUT = 3
+LUT_SIZE = 1000
+
+
+def lut_e(s, nu):
+    """E(arcsin s, nu) through the lookup tables (reciprocal modulus for nu > 1)."""
+    return lib().or_lut_e(float(s), float(nu))
+
+
+def lut_entry(i, j):
+    """Node (s_i, nu_j) of the tables (0-based) and the stored E~, F~ there."""
+    v = [_d(0) for _ in range(4)]
+    lib().or_lut_entry(int(i), int(j), *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+def lut_set_size(n):
+    """Points per axis of the tables (the method uses 1000; other sizes are for
+    convergence tests).  Rebuilds the tables on the next use."""
+    lib().or_lut_set_size(int(n))
 
 
 def _common(prob, h, nf, mode, step):

@@ -20,6 +20,10 @@
  *                          (Lemma exact_integral, appendix on elliptic integrals)
  *   point coefficients     Alg. 2, Eq. def_f_point, midpoint tensor rule (Prop. 2)
  *   trapezoidal I_l        Eq. trapezoid_Il (cylinder; the planar I_l stays exact)
+ *   lookup-table I_l       Sec. 4.2 (LUT paragraph): E~(s, nu) = E(arcsin s, nu) and
+ *                          F~(s, nu) = F(arcsin s, nu) on the power-law grid of
+ *                          Eq. LUT_sampling, bilinear interpolation, nu > 1 through
+ *                          the reciprocal-modulus transformation Eq. reciprocal_modulus
  *   coarse area grid       Remark 1: the area of each shell of step fine bins,
  *                          split evenly over those bins (step = 1: exact)
  *   adjoint A^T            Alg. 5, 6, 7 (transpose of the downsampling,
@@ -57,6 +61,7 @@
 #define OR_MODE_SURFACE 0
 #define OR_MODE_POINT 1
 #define OR_MODE_TRAPEZOID 2
+#define OR_MODE_LUT 3
 
 /* ------------------------------------------------------------------------- */
 /* Carlson symmetric elliptic integrals (DLMF 19.36.1 and 19.36.2)            */
@@ -134,6 +139,132 @@ double or_ellip_f(double phi, double m)
     double y = 1.0 - m * s * s;
     if (y < 0.0) y = 0.0;
     return s * or_carlson_rf(c * c, y, 1.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lookup tables of E~ and F~ (Sec. 4.2, LUT paragraph)                       */
+/* ------------------------------------------------------------------------- */
+
+/* Both axes use the grid of Eq. LUT_sampling, x_n = (1 - eps)[1 - (1 - t_n)^4],
+   t_n = (n - 1)/(N - 1), n = 1..N, eps = 1e-16; here indices run from 0.  The
+   table holds, for every node (s_i, nu_j), the pair E~, F~ at
+   tab[2 (j N + i)] and tab[2 (j N + i) + 1], in double precision like every
+   other array of the method. */
+static const double lut_eps = 1e-16;
+static int lut_size = 1000;
+static int lut_built = 0;
+static double* lut_tab = NULL;
+
+static double lut_node(int n, int N)
+{
+    double t = 1.0 - (double)n / (N - 1);
+    return (1.0 - lut_eps) * (1.0 - t * t * t * t);
+}
+
+static void lut_build(void)
+{
+    int N = lut_size;
+    free(lut_tab);
+    lut_tab = (double*)malloc(sizeof(double) * 2 * (size_t)N * N);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < N; ++j) {
+        double nu = lut_node(j, N);
+        for (int i = 0; i < N; ++i) {
+            double s = lut_node(i, N);
+            double c2 = (1.0 - s) * (1.0 + s);   /* cos^2(arcsin s) */
+            double y = 1.0 - nu * s * s;
+            double e = 0.0, f = 0.0;
+            if (s > 0.0) {
+                double rf = or_carlson_rf(c2, y, 1.0);
+                f = s * rf;
+                e = f - (nu / 3.0) * s * s * s * or_carlson_rd(c2, y, 1.0);
+            }
+            lut_tab[2 * ((size_t)j * N + i)] = e;
+            lut_tab[2 * ((size_t)j * N + i) + 1] = f;
+        }
+    }
+    lut_built = 1;
+}
+
+static void lut_ensure(void)
+{
+    if (!lut_built) lut_build();
+}
+
+/* table size per axis (tests only; the method uses 1000) */
+void or_lut_set_size(int n)
+{
+    if (n >= 2 && n != lut_size) {
+        lut_size = n;
+        lut_built = 0;
+    }
+}
+
+/* the cell [x_n, x_{n+1}] of the grid holding x and the position in it: the
+   inverse of Eq. LUT_sampling, t = 1 - (1 - x/(1 - eps))^(1/4), two square roots */
+static void lut_locate(double x, int N, int* n, double* w)
+{
+    double y = x / (1.0 - lut_eps);
+    if (y > 1.0) y = 1.0;
+    if (y < 0.0) y = 0.0;
+    double t = 1.0 - sqrt(sqrt(1.0 - y));
+    double p = t * (N - 1);
+    int k = (int)floor(p);
+    if (k > N - 2) k = N - 2;
+    *n = k;
+    *w = p - k;
+}
+
+/* bilinear interpolation of E~ and F~ at (s, nu) in [0, 1]^2 */
+static void lut_interp(double s, double nu, double* E, double* F)
+{
+    int N = lut_size, i, j;
+    double ws, wn;
+    lut_locate(s, N, &i, &ws);
+    lut_locate(nu, N, &j, &wn);
+    double e = 0.0, f = 0.0;
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            double wt = (di ? ws : 1.0 - ws) * (dj ? wn : 1.0 - wn);
+            const double* t = lut_tab + 2 * ((size_t)(j + dj) * N + (i + di));
+            e += wt * t[0];
+            f += wt * t[1];
+        }
+    *E = e;
+    *F = f;
+}
+
+/* E(theta, nu) for theta in [0, pi/2] with nu sin^2(theta) <= 1, from s =
+   sin(theta), by the tables: E~(s, nu) when nu <= 1, otherwise Eq.
+   reciprocal_modulus, E = sqrt(nu) [E~(sqrt(nu) s, 1/nu) - (1 - 1/nu) F~(sqrt(nu) s, 1/nu)]
+   (arcsin(sqrt(nu) s) is the amplitude the tables are indexed by through its sine) */
+static double lut_e(double s, double nu)
+{
+    double E, F;
+    if (nu <= 1.0) {
+        lut_interp(s, nu, &E, &F);
+        return E;
+    }
+    double sq = sqrt(nu);
+    lut_interp(sq * s, 1.0 / nu, &E, &F);
+    return sq * (E - (1.0 - 1.0 / nu) * F);
+}
+
+/* for tests: E(theta, nu) by the tables, from s = sin(theta) */
+double or_lut_e(double s, double nu)
+{
+    lut_ensure();
+    return lut_e(s, nu);
+}
+
+/* for tests: the table entries at node (i, j) and the node coordinates */
+void or_lut_entry(int i, int j, double* s, double* nu, double* E, double* F)
+{
+    lut_ensure();
+    *s = lut_node(i, lut_size);
+    *nu = lut_node(j, lut_size);
+    *E = lut_tab[2 * ((size_t)j * lut_size + i)];
+    *F = lut_tab[2 * ((size_t)j * lut_size + i) + 1];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -425,7 +556,7 @@ typedef struct { double al, be, I; } otriple;
 
 /* alpha/beta = clamped Phi(v, r) (Eq. alphabeta) and I (Eq. plane_primitive /
    Eq. cyl_Il) for one quadrant at radius r. */
-static otriple quad_edge(const opair* P, const oquad* q, double r, int trap)
+static otriple quad_edge(const opair* P, const oquad* q, double r, int mode)
 {
     otriple T;
     double r2 = r * r;
@@ -467,7 +598,7 @@ static otriple quad_edge(const opair* P, const oquad* q, double r, int trap)
     }
     double Kc = r2 - dm * dm;   /* 2 R rho + b(r) */
     if (!(T.be > T.al) || !(Kc > 0.0)) { T.I = 0.0; return T; }
-    if (trap) {
+    if (mode == OR_MODE_TRAPEZOID) {
         /* Eq. trapezoid_Il: the level curve u -> Psi(u, r) = sqrt(r^2 - psi(u))
            replaced by the chord between its end points.  An end point inside
            (a, b) lies on its line by definition (Eq. alphabeta), so Psi there
@@ -478,18 +609,21 @@ static otriple quad_edge(const opair* P, const oquad* q, double r, int trap)
         return T;
     }
     double nu = 4.0 * R * rho / Kc;
-    T.I = 2.0 * sqrt(Kc) * (ellip_e_sc(sb, cb, nu) - ellip_e_sc(sa, ca, nu));
+    if (mode == OR_MODE_LUT)
+        T.I = 2.0 * sqrt(Kc) * (lut_e(sb, nu) - lut_e(sa, nu));
+    else
+        T.I = 2.0 * sqrt(Kc) * (ellip_e_sc(sb, cb, nu) - ellip_e_sc(sa, ca, nu));
     return T;
 }
 
 /* |D^l| summed over quadrants (Eq. area_D_l_xi, Eq. swept_u) given the triples at
    the previous edge; updates the triples to the new edge (Alg. 4). */
-static double alg4_step(const opair* P, otriple* tri, double r, int trap)
+static double alg4_step(const opair* P, otriple* tri, double r, int mode)
 {
     double area = 0.0;
     for (int k = 0; k < P->nq; ++k) {
         const oquad* q = &P->q[k];
-        otriple T = quad_edge(P, q, r, trap);
+        otriple T = quad_edge(P, q, r, mode);
         area += P->J0 * ((T.al - tri[k].al) * q->d + T.I - tri[k].I - (T.be - tri[k].be) * q->c);
         tri[k] = T;
     }
@@ -517,7 +651,7 @@ double or_shell_area(const double* tr, const double* x, double r0, double r1)
 
 /* Bin range (Eq. rmin_rmax) and the areas of every bin in it, carrying the
    triples from edge to edge (Alg. 3 + Alg. 4).  Returns the count, or -1. */
-static long pair_areas(const double* tr, const double* x, double c, double t0, double ufs, int trap,
+static long pair_areas(const double* tr, const double* x, double c, double t0, double ufs, int mode,
                        long* lmin, long* lmax, double* out, long cap)
 {
     opair P;
@@ -530,7 +664,7 @@ static long pair_areas(const double* tr, const double* x, double c, double t0, d
     if (l1 - l0 + 1 > cap) return -1;
     otriple tri[4];
     alg4_init(&P, tri);
-    for (long l = l0; l <= l1; ++l) out[l - l0] = alg4_step(&P, tri, c * (t0 + l / ufs), trap);
+    for (long l = l0; l <= l1; ++l) out[l - l0] = alg4_step(&P, tri, c * (t0 + l / ufs), mode);
     return l1 - l0 + 1;
 }
 
@@ -568,13 +702,14 @@ static long shell_split(int step, long* l0, long cnt, const double* a, double* o
     return s1 - s0 + 1;
 }
 
-/* The areas a surface method uses for one pair: exact (mode 0) or with the
-   trapezoidal I_l (mode 2), on the fine bins (step 1) or split from the shells
-   of the coarse area grid (step > 1). */
-long or_pair_areas_mode(const double* tr, const double* x, double c, double t0, double ufs, int mode,
-                        int step, long* lmin, long* lmax, double* out, long cap)
+/* The areas a surface method uses for one pair: exact (mode 0), with the
+   trapezoidal I_l (mode 2) or the lookup-table I_l (mode 3), on the fine bins
+   (step 1) or split from the shells of the coarse area grid (step > 1).  The
+   tables must exist (lut_ensure) before a mode-3 call. */
+static long pair_areas_mode(const double* tr, const double* x, double c, double t0, double ufs, int mode,
+                            int step, long* lmin, long* lmax, double* out, long cap)
 {
-    long cnt = pair_areas(tr, x, c, t0, ufs, mode == OR_MODE_TRAPEZOID, lmin, lmax, out, cap);
+    long cnt = pair_areas(tr, x, c, t0, ufs, mode, lmin, lmax, out, cap);
     if (cnt <= 0 || step <= 1) return cnt;
     double* fine = (double*)malloc(sizeof(double) * cnt);
     memcpy(fine, out, sizeof(double) * cnt);
@@ -582,6 +717,13 @@ long or_pair_areas_mode(const double* tr, const double* x, double c, double t0, 
     free(fine);
     if (n >= 0) *lmax = *lmin + n - 1;
     return n;
+}
+
+long or_pair_areas_mode(const double* tr, const double* x, double c, double t0, double ufs, int mode,
+                        int step, long* lmin, long* lmax, double* out, long cap)
+{
+    if (mode == OR_MODE_LUT) lut_ensure();
+    return pair_areas_mode(tr, x, c, t0, ufs, mode, step, lmin, lmax, out, cap);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -644,6 +786,7 @@ static void op_init(oop* o, const double* tr, int K, const long* n, const double
     o->w = w; o->h = h; o->nf = nf; o->hlen = hlen;
     o->c = c; o->fs = fs; o->t0 = t0; o->L = L; o->U = U; o->mode = mode; o->q1 = q1; o->q2 = q2;
     long nl = nf + hlen - 1;
+    if (mode == OR_MODE_LUT) lut_ensure();
     o->Mlo = 1 - nl;
     o->Mhi = (long)U * L - nf;
 }
@@ -680,7 +823,7 @@ static void fcoef_range(const oop* o, int k, const double* coef, int B, long N, 
         voxel_xyz(o, i, x);
         if (o->mode != OR_MODE_POINT) {
             long l0, l1;
-            long cnt = or_pair_areas_mode(tr, x, o->c, o->t0, ufs, o->mode, o->step, &l0, &l1, tmp, cap);
+            long cnt = pair_areas_mode(tr, x, o->c, o->t0, ufs, o->mode, o->step, &l0, &l1, tmp, cap);
             for (long j = 0; j < cnt; ++j) {
                 long l = l0 + j;
                 if (l < o->Mlo || l > o->Mhi) continue;
@@ -851,7 +994,7 @@ void or_adjoint(const double* tr, int K, const long* n, const double* origin, do
                 const double* t = tr + 16 * k;
                 if (mode != OR_MODE_POINT) {
                     long l0, l1;
-                    long cnt = or_pair_areas_mode(t, x, c, t0, ufs, mode, o.step, &l0, &l1, tmp, cap);
+                    long cnt = pair_areas_mode(t, x, c, t0, ufs, mode, o.step, &l0, &l1, tmp, cap);
                     for (long j = 0; j < cnt; ++j) {
                         long l = l0 + j;
                         if (l < o.Mlo || l > o.Mhi) continue;
