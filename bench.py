@@ -183,6 +183,89 @@ def run_next(args, prob, kern, B, pairs, torch, dev, log):
     return rows
 
 
+def run_lib(torch, dev, log):
+    """The LIB scale (Sec. 2.6), synthesised: 200^3 voxels, 11 520 cylinders,
+    L = 2688.  (1) The forward restricted to the nonzero voxels at U = 61 with an
+    area per fine bin, in FP64: the paper's exact reference application.  (2)
+    The dense A + A^T at U = 11, area per native sample and per fine bin, on a
+    sub-scan of one angle x 5 translations (320 cylinders), scaled by K to the
+    whole scan: the operator of the paper's reconstruction.  Errors against the
+    oracle on a few transducers / voxels."""
+    import numpy as np
+    import oracle as O
+    import pat_inputs as P
+    from paper_2609_29253_amd.operator import PatOperator
+
+    def rl2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def events(fn, reps=1):
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(reps):
+            out = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    rows = {}
+    p = P.config_lib(U=61)
+    nz = int((p.coef != 0).sum())
+    log(f"[bench] lib: {p.name} N={p.N} K={p.K} L={p.L} U={p.U}, {nz} nonzero voxels")
+    op = PatOperator.from_problem(p, mode="closed", precision="fp64")
+    coef = torch.tensor(p.coef, dtype=torch.float64, device=dev)
+    ms, s = events(lambda: op.forward(coef, sparse=True))
+    evals = op.query(7)
+    ks = np.array([1234, 7777], dtype=np.int32)
+    got = s[:, torch.tensor(ks, device=dev).long()].cpu().numpy()
+    ws = op.query(5)
+    op.close()
+    del s, coef
+    t = time.perf_counter()
+    ref = O.forward(p, ksub=ks)
+    log(f"[bench] lib: oracle on transducers {ks.tolist()}: {time.perf_counter() - t:.1f}s")
+    pairs = float(nz) * p.K
+    rows["lib_sparse_forward_U61_step1_fp64"] = {
+        "workload": p.name, "U": p.U, "area_step": 1, "nonzero_voxels": nz, "ms_forward": round(ms, 3),
+        "pairs_per_s": pairs / (ms * 1e-3), "area_evaluations": evals, "workspace_bytes": ws,
+        "paper_seconds": 7200.0, "paper_pairs_per_s": 3.8e4,
+        "rel_err_vs_oracle": {"forward_transducers": ks.tolist(), "forward": rl2(got, ref)}}
+    log(f"[bench] lib sparse forward: {rows['lib_sparse_forward_U61_step1_fp64']}")
+
+    sub = P.config_lib(angles=[0], translations=[0, 3, 7, 11, 14], U=11)
+    scale = 11520.0 / sub.K
+    ks = np.array([5, 200], dtype=np.int32)
+    vs = np.linspace(0, sub.N - 1, 8).astype(np.int64)
+    vs[3] = int(np.flatnonzero(sub.coef[0])[0])
+    for step, prec in ((11, "fp32"), (11, "fp64"), (1, "fp64")):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        op = PatOperator.from_problem(sub, mode="closed", precision=prec, area_step=step)
+        coef = torch.tensor(sub.coef, dtype=dt, device=dev)
+        y = torch.tensor(sub.y, dtype=dt, device=dev)
+        f_ms, s = events(lambda: op.forward(coef))
+        a_ms, z = events(lambda: op.adjoint(y))
+        evals = op.query(7)
+        s = s[:, torch.tensor(ks, device=dev).long()].double().cpu().numpy()
+        z = z[:, torch.tensor(vs, device=dev)].double().cpu().numpy()
+        op.close()
+        del coef, y
+        t = time.perf_counter()
+        ref = (O.forward(sub, ksub=ks, step=step), O.adjoint(sub, vsub=vs, step=step))
+        log(f"[bench] lib: oracle sample {time.perf_counter() - t:.1f}s")
+        row = {"workload": sub.name, "U": sub.U, "area_step": step, "transducers": sub.K,
+               "ms_forward": round(f_ms, 3), "ms_adjoint": round(a_ms, 3),
+               "pairs_per_s": float(sub.N) * sub.K / ((f_ms + a_ms) * 1e-3), "area_evaluations": evals,
+               "full_scan_seconds_per_A_AT": round((f_ms + a_ms) * 1e-3 * scale, 2),
+               "paper_seconds_per_iteration": 15.8 * 3600 / 30,
+               "rel_err_vs_oracle_same_step": {"forward": rl2(s, ref[0]), "adjoint": rl2(z, ref[1])}}
+        rows[f"lib_dense_U11_step{step}_{prec}"] = row
+        log(f"[bench] lib dense: {row}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +281,9 @@ def main():
     ap.add_argument("--next", action="store_true",
                     help="also time the approximate variants (trapezoidal cylinder I_l on the workload; the "
                          "coarse area grid on the 128^3 cylinder workload at U = 4) with their errors")
+    ap.add_argument("--lib", action="store_true",
+                    help="only the LIB-scale rows (sparse forward at U = 61, dense A + A^T at U = 11 on a "
+                         "sub-scan), printed as one JSON object instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator is built and timed on a single MI355X; "
@@ -207,6 +293,11 @@ def main():
     import numpy as np
     import torch
     from paper_2609_29253_amd.operator import PatOperator, build_kernel
+
+    if args.lib:
+        dev = torch.device("cuda", 0)
+        print(json.dumps({"lib_rows": run_lib(torch, dev, log)}), flush=True)
+        return
 
     t_build = time.perf_counter()
     prob = build_workload(args.workload)

@@ -156,6 +156,15 @@ pat_status pat_set_geometry(pat_ctx* ctx, const pat_transducer* tr, int32_t K,
 pat_status pat_forward(pat_ctx* ctx, const void* coef, void* signal, int32_t batch,
                        void* hip_stream);
 
+/* A restricted to the support of the coefficients (Alg. 3 with its sum over voxels
+ * limited to the voxels where some volume's coefficient is nonzero; the paper
+ * computes its reference signals this way on sparse phantoms).  Same arguments and
+ * result as pat_forward up to summation order; the support is rebuilt on the device
+ * from `coef` at every call (no host synchronisation).  Surface methods only:
+ * PAT_E_UNSUPPORTED for PAT_AREA_QUADRATURE. */
+pat_status pat_forward_sparse(pat_ctx* ctx, const void* coef, void* signal, int32_t batch,
+                              void* hip_stream);
+
 /* coef = A^T signal (Alg. 5 with Alg. 6 or Alg. 7).  Same layouts as forward. */
 pat_status pat_adjoint(pat_ctx* ctx, const void* signal, void* coef, int32_t batch,
                        void* hip_stream);

@@ -43,6 +43,7 @@ struct pat_ctx {
     double* d_f = nullptr;
     void* d_W = nullptr;
     double* d_z = nullptr;
+    int32_t* d_sup = nullptr;       // support list [N], per-brick counts [nbricks], offsets [nbricks + 1]
 };
 
 namespace {
@@ -73,7 +74,8 @@ pat_status fail(pat_ctx* c, pat_status st, const std::string& msg)
 void free_dev(pat_ctx* c)
 {
     void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, (void**)&c->d_G,
-                     (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z};
+                     (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z,
+                     (void**)&c->d_sup};
     for (void** p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -360,6 +362,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     const size_t fbytes = (size_t)p.max_batch * K * Mcount * sizeof(double);
     const size_t wbytes = (size_t)p.max_batch * K * Mcount * rs;
     const size_t zbytes = (size_t)p.max_batch * N * sizeof(double);
+    const size_t sbytes = surface ? ((size_t)N + 2 * (size_t)nbricks + 1) * sizeof(int32_t) : 0;
     auto dmalloc = [&](void** ptr, size_t bytes) -> bool {
         if (bytes == 0) bytes = 8;
         return hipMalloc(ptr, bytes) == hipSuccess;
@@ -367,13 +370,14 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!dmalloc((void**)&c->d_tr, sizeof(TrDev) * K) || !dmalloc((void**)&c->d_kperm, sizeof(int32_t) * K) ||
         !dmalloc((void**)&c->d_scale, sizeof(double) * Mcount) || !dmalloc((void**)&c->d_G, sizeof(double) * jcnt) ||
         !dmalloc((void**)&c->d_f, fbytes) || !dmalloc(&c->d_W, wbytes) || !dmalloc((void**)&c->d_z, zbytes) ||
+        (surface && !dmalloc((void**)&c->d_sup, sbytes)) ||
         (Q > 0 && (!dmalloc((void**)&c->d_qpts, sizeof(double) * qp.size()) ||
                    !dmalloc((void**)&c->d_qdA, sizeof(double) * K)))) {
         (void)hipGetLastError();
         free_dev(c);
         return fail(c, PAT_E_OOM, "device allocation failed");
     }
-    c->ws_bytes = fbytes + wbytes + zbytes;
+    c->ws_bytes = fbytes + wbytes + zbytes + sbytes;
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -443,6 +447,11 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     Lp.f = c->d_f;
     Lp.W = c->d_W;
     Lp.z64 = c->d_z;
+    if (surface) {
+        Lp.sup_list = c->d_sup;
+        Lp.sup_cnt = c->d_sup + N;
+        Lp.sup_off = c->d_sup + N + nbricks;
+    }
 
     c->K = K;
     c->N = N;
@@ -457,27 +466,37 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     return PAT_OK;
 }
 
-static pat_status run(pat_ctx* c, const void* in, void* out, int32_t batch, void* stream, bool fwd)
+enum class Op { forward, forward_sparse, adjoint };
+
+static pat_status run(pat_ctx* c, const void* in, void* out, int32_t batch, void* stream, Op op)
 {
     if (!c) return PAT_E_ARG;
     if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
     if (!in || !out || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
+    if (op == Op::forward_sparse && c->mode == PAT_AREA_QUADRATURE)
+        return fail(c, PAT_E_UNSUPPORTED, "the sparse forward serves the surface methods");
     DevGuard guard(c->device);
     if (!guard.ok) return fail(c, PAT_E_DEVICE, "hipSetDevice failed");
-    hipError_t e = fwd ? launch_forward(c->plan, in, out, batch, (hipStream_t)stream)
-                       : launch_adjoint(c->plan, in, out, batch, (hipStream_t)stream);
+    hipError_t e = op == Op::forward        ? launch_forward(c->plan, in, out, batch, (hipStream_t)stream)
+                   : op == Op::forward_sparse ? launch_forward_sparse(c->plan, in, out, batch, (hipStream_t)stream)
+                                              : launch_adjoint(c->plan, in, out, batch, (hipStream_t)stream);
     if (e != hipSuccess) return fail(c, PAT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
     return PAT_OK;
 }
 
 pat_status pat_forward(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
 {
-    return run(c, coef, signal, batch, stream, true);
+    return run(c, coef, signal, batch, stream, Op::forward);
+}
+
+pat_status pat_forward_sparse(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
+{
+    return run(c, coef, signal, batch, stream, Op::forward_sparse);
 }
 
 pat_status pat_adjoint(pat_ctx* c, const void* signal, void* coef, int32_t batch, void* stream)
 {
-    return run(c, signal, coef, batch, stream, false);
+    return run(c, signal, coef, batch, stream, Op::adjoint);
 }
 
 pat_status pat_query(const pat_ctx* c, int32_t what, double* out)

@@ -29,9 +29,14 @@ struct LaunchPlan {
     double* f;              // [max_batch][K][Mcount] forward workspace
     void* W;                // [max_batch][K][Mcount] adjoint workspace (float or double)
     double* z64;            // [max_batch][N] adjoint FP64 partial sums
+    int32_t* sup_list;      // [N] support of the coefficients (sparse forward)
+    int32_t* sup_cnt;       // [nbricks] nonzero voxels per brick
+    int32_t* sup_off;       // [nbricks + 1] their exclusive prefix sums (last entry: total)
 };
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
+// A restricted to the voxels where some volume's coefficient is nonzero (same result)
+hipError_t launch_forward_sparse(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
 hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_t s);
 hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s);
 

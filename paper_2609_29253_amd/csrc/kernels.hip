@@ -83,6 +83,37 @@ __device__ __forceinline__ void brick_setup(const KParams& P, Brick& Bk)
     Bk.lo[2] = P.origin[2] + z0 * P.w; Bk.hi[2] = P.origin[2] + z1 * P.w;
 }
 
+// Sparse forward: work-group g takes entries 256 g .. 256 g + 255 of the support
+// list (nonzero voxels listed brick by brick, so they lie in a few neighbouring
+// bricks) and the box of those voxels.  Returns false for the whole work-group
+// when g is past the end of the list.
+__device__ __forceinline__ bool brick_setup_sparse(const KParams& P, Brick& Bk)
+{
+    __shared__ int bmin[3], bmax[3];
+    const int64_t total = *P.sup_total;
+    const int64_t g0 = (int64_t)blockIdx.x * kThreads;
+    if (g0 >= total) return false;
+    if (threadIdx.x < 3) { bmin[threadIdx.x] = 0x7fffffff; bmax[threadIdx.x] = -1; }
+    __syncthreads();
+    const int64_t e = g0 + threadIdx.x;
+    Bk.valid = e < total;
+    const int64_t idx = P.sup_list[Bk.valid ? e : g0];
+    Bk.idx = Bk.valid ? idx : 0;
+    Bk.ix = (int)(idx % P.n[0]);
+    Bk.iy = (int)((idx / P.n[0]) % P.n[1]);
+    Bk.iz = (int)(idx / (P.n[0] * P.n[1]));
+    atomicMin(&bmin[0], Bk.ix); atomicMax(&bmax[0], Bk.ix);
+    atomicMin(&bmin[1], Bk.iy); atomicMax(&bmax[1], Bk.iy);
+    atomicMin(&bmin[2], Bk.iz); atomicMax(&bmax[2], Bk.iz);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Bk.lo[a] = P.origin[a] + bmin[a] * P.w;
+        Bk.hi[a] = P.origin[a] + bmax[a] * P.w;
+    }
+    return true;
+}
+
 // bins that any voxel of the brick can reach on transducer T (bounding sphere)
 __device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, const TrDev& T, int& wlo,
                                              int& whi)
@@ -302,14 +333,18 @@ template <class AT, class Real, bool TRAP> struct PairOf<1, AT, Real, TRAP> {
 // forward, closed-form areas
 // ---------------------------------------------------------------------------
 
-template <int SHAPE, class AT, int NB, class Real, bool TRAP>
+template <int SHAPE, class AT, int NB, class Real, bool TRAP, bool SPARSE>
 __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
     extern __shared__ double hist[];   // [NB][kHist]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     Brick Bk;
-    brick_setup(P, Bk);
+    if (SPARSE) {
+        if (!brick_setup_sparse(P, Bk)) return;
+    } else {
+        brick_setup(P, Bk);
+    }
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -624,6 +659,74 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
 }
 
 // ---------------------------------------------------------------------------
+// support of the coefficients (the voxels the forward's sum over voxels needs)
+// ---------------------------------------------------------------------------
+
+template <class Real>
+__device__ __forceinline__ bool voxel_nonzero(const KParams& P, const Brick& Bk, const Real* coef, int B)
+{
+    bool nz = false;
+    if (Bk.valid)
+        for (int b = 0; b < B; ++b) nz |= coef[b * P.N + Bk.idx] != Real(0);
+    return nz;
+}
+
+// nonzero voxels per brick
+template <class Real>
+__global__ __launch_bounds__(kThreads) void k_support_count(KParams P, const Real* __restrict__ coef, int B,
+                                                             int32_t* __restrict__ cnt)
+{
+    Brick Bk;
+    brick_setup(P, Bk);
+    const int c = __syncthreads_count(voxel_nonzero(P, Bk, coef, B));
+    if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+// exclusive prefix sums of the per-brick counts (one work-group); off[n] = total
+__global__ __launch_bounds__(kThreads) void k_support_scan(const int32_t* __restrict__ cnt, int n,
+                                                            int32_t* __restrict__ off)
+{
+    __shared__ int s[kThreads];
+    int carry = 0;
+    for (int base = 0; base < n; base += kThreads) {
+        const int i = base + threadIdx.x;
+        const int v = i < n ? cnt[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kThreads; o <<= 1) {
+            const int t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n) off[i] = carry + s[threadIdx.x] - v;
+        carry += s[kThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[n] = carry;
+}
+
+// the nonzero voxels of each brick at the brick's offset, in thread order
+template <class Real>
+__global__ __launch_bounds__(kThreads) void k_support_write(KParams P, const Real* __restrict__ coef, int B,
+                                                             const int32_t* __restrict__ off,
+                                                             int32_t* __restrict__ list)
+{
+    __shared__ int wcount[kThreads / 64];
+    Brick Bk;
+    brick_setup(P, Bk);
+    const bool nz = voxel_nonzero(P, Bk, coef, B);
+    const unsigned long long m = __ballot(nz);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[w] = __popcll(m);
+    __syncthreads();
+    int base = off[blockIdx.x];
+    for (int v = 0; v < w; ++v) base += wcount[v];
+    if (nz) list[base + rank] = (int32_t)Bk.idx;
+}
+
+// ---------------------------------------------------------------------------
 // temporal stage
 // ---------------------------------------------------------------------------
 
@@ -674,15 +777,15 @@ __global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ sc
 
 namespace {
 
-template <int SHAPE, class AT, class Real, bool TRAP>
+template <int SHAPE, class AT, class Real, bool TRAP, bool SPARSE = false>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
     size_t sh = (size_t)nb * kHist * sizeof(double);
     switch (nb) {
-    case 1: k_fwd_closed<SHAPE, AT, 1, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 2: k_fwd_closed<SHAPE, AT, 2, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 4: k_fwd_closed<SHAPE, AT, 4, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    default: k_fwd_closed<SHAPE, AT, 8, Real, TRAP><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 1: k_fwd_closed<SHAPE, AT, 1, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 2: k_fwd_closed<SHAPE, AT, 2, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 4: k_fwd_closed<SHAPE, AT, 4, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    default: k_fwd_closed<SHAPE, AT, 8, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     }
     return hipGetLastError();
 }
@@ -740,12 +843,19 @@ int grid_fill_blocks(int64_t n)
 }
 
 template <class Real>
-hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hipStream_t s)
+hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hipStream_t s, bool sparse)
 {
     hipError_t e;
     const int64_t nf = (int64_t)B * L.base.K * L.base.Mcount;
     k_fill<<<grid_fill_blocks(nf), 256, 0, s>>>(L.f, nf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (sparse) {
+        // support of the whole batch: the voxels with a nonzero coefficient in any volume
+        k_support_count<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_cnt);
+        k_support_scan<<<1, kThreads, 0, s>>>(L.sup_cnt, L.nbricks, L.sup_off);
+        k_support_write<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_off, L.sup_list);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (int b0 = 0; b0 < B;) {
         const int nb = chunk_nb(B - b0);
         for (int g = 0; g < L.ngroups; ++g) {
@@ -758,7 +868,14 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
             dim3 grid(L.nbricks, (G.nk + G.kchunk_fwd - 1) / G.kchunk_fwd);
             const Real* cb = coef + (int64_t)b0 * P.N;
             double* fb = L.f + (int64_t)b0 * P.K * P.Mcount;
+            if (sparse) {
+                P.sup_list = L.sup_list;
+                P.sup_total = L.sup_off + L.nbricks;
+            }
             if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
+            else if (sparse && G.shape == 0) e = fwd_closed_nb<0, Real, Real, false, true>(nb, grid, P, cb, fb, s);
+            else if (sparse && L.mode == 2) e = fwd_closed_nb<1, double, Real, true, true>(nb, grid, P, cb, fb, s);
+            else if (sparse) e = fwd_closed_nb<1, double, Real, false, true>(nb, grid, P, cb, fb, s);
             else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, false>(nb, grid, P, cb, fb, s);
             else if (L.mode == 2) e = fwd_closed_nb<1, double, Real, true>(nb, grid, P, cb, fb, s);
             else e = fwd_closed_nb<1, double, Real, false>(nb, grid, P, cb, fb, s);
@@ -833,8 +950,15 @@ hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s)
 {
-    if (L.fp64) return forward_t<double>(L, (const double*)coef, (double*)sig, B, s);
-    return forward_t<float>(L, (const float*)coef, (float*)sig, B, s);
+    if (L.fp64) return forward_t<double>(L, (const double*)coef, (double*)sig, B, s, false);
+    return forward_t<float>(L, (const float*)coef, (float*)sig, B, s, false);
+}
+
+hipError_t launch_forward_sparse(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s)
+{
+    if (L.mode == 1) return hipErrorNotSupported;
+    if (L.fp64) return forward_t<double>(L, (const double*)coef, (double*)sig, B, s, true);
+    return forward_t<float>(L, (const float*)coef, (float*)sig, B, s, true);
 }
 
 hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s)

@@ -50,6 +50,9 @@ struct KParams {
     int32_t nbx, nby, nbz;  // bricks per axis
     int32_t B;              // volumes in this launch (<= kMaxNB)
     int64_t N;
+    // support of the coefficients (forward restricted to nonzero voxels)
+    const int32_t* sup_list;    // voxel indices, brick by brick
+    const int32_t* sup_total;   // [1] number of entries
     // quadrature
     const double* qpts;     // [K][Q][3] global point coordinates
     const double* qdA;      // [K] cell area (dr^2 units)

@@ -116,13 +116,14 @@ class PatOperator:
             raise ValueError(f"bad shape {tuple(x.shape)} (batch must be 1..{self.max_batch})")
         return x, B
 
-    def forward(self, coef: torch.Tensor) -> torch.Tensor:
-        """coef [B, N] (or [N]) -> signals [B, K, L]."""
+    def forward(self, coef: torch.Tensor, sparse: bool = False) -> torch.Tensor:
+        """coef [B, N] (or [N]) -> signals [B, K, L].  sparse=True sums only over the
+        voxels where some volume is nonzero (same result; for sparse phantoms)."""
         squeeze = coef.dim() == 1
         coef, B = self._prep(coef, self.N)
         out = torch.empty((B, self.K, self.L), dtype=self.dtype, device=self.device)
-        st = L.lib().pat_forward(self._ctx, ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
-                                 self._stream())
+        fn = L.lib().pat_forward_sparse if sparse else L.lib().pat_forward
+        st = fn(self._ctx, ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(out.data_ptr()), B, self._stream())
         L.check(st, self._ctx)
         return out[0] if squeeze else out
 

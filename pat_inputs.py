@@ -242,6 +242,35 @@ def arc_cylinder_array(n_elem: int, n_rot: int, arc_radius: float, R: float,
     return Transducers(np.array(rows))
 
 
+def lib_scan_array(n_angles: int = 12, n_trans: int = 15, n_elem: int = 64, pitch: float = 0.298e-3,
+                   width: float = 0.25e-3, elevation: float = 7.5e-3, R: float = 25e-3,
+                   distance: float = 25e-3, sweep: float = 10e-3) -> Transducers:
+    """A translate-rotate scan of a linear array with the LIB system's element
+    shape (Sec. 2.6), synthesised: the measured positions are not public.
+
+    ``n_elem`` cylindrically focused elements (focal distance R, elevation chord
+    ``elevation``, width ``width`` along the array axis = the straight length)
+    at ``pitch`` along z, the array facing the origin from ``distance`` in the
+    xy plane; rotated to ``n_angles`` angles over 180 degrees about z and, at each
+    angle, translated to ``n_trans`` positions spread over ``sweep`` along the
+    tangential direction, so that the focal line sweeps across the volume.
+    Transducer index = (angle * n_trans + translation) * n_elem + element."""
+    theta_max = math.asin(elevation / (2.0 * R))
+    rows = []
+    zs = (np.arange(n_elem) - (n_elem - 1) / 2.0) * pitch
+    taus = np.linspace(-sweep / 2.0, sweep / 2.0, n_trans) if n_trans > 1 else np.zeros(1)
+    for a in range(n_angles):
+        phi = math.pi * a / n_angles
+        out = np.array([math.cos(phi), math.sin(phi), 0.0])
+        tang = np.array([-math.sin(phi), math.cos(phi), 0.0])
+        n = -out
+        for tau in taus:
+            for z in zs:
+                P = distance * out + tau * tang + np.array([0.0, 0.0, z])
+                rows.append(cylinder(P + R * n, [0.0, 0.0, 1.0], -n, R, theta_max, width / 2.0))
+    return Transducers(np.array(rows))
+
+
 # ----------------------------------------------------------------------------
 # phantoms
 # ----------------------------------------------------------------------------
@@ -301,6 +330,29 @@ def polylines(grid: Grid, rng, count: int, n_seg: int = 10, seg_len: float = 0.8
                 t = np.clip(((X - p) @ ab) / float(ab @ ab), 0.0, 1.0)
                 dist2 = np.sum((X - (p + t[..., None] * ab)) ** 2, axis=-1)
                 _add_local(out, idx, np.exp(-dist2 / (2.0 * tube_sigma ** 2)), "max")
+            p = q
+            d = _unit(d + 0.5 * rng.normal(size=3))
+    return out.ravel()
+
+
+def vessels(grid: Grid, rng, count: int, radius: float, n_seg: int = 10, seg_len: float = 0.8e-3,
+            inner: float = 0.8) -> np.ndarray:
+    """Binary vessel labels: 1 within ``radius`` of ``count`` random-walk
+    polylines (the walk of ``polylines``), 0 elsewhere: a sparse support."""
+    out = np.zeros((grid.n[2], grid.n[1], grid.n[0]))
+    half = np.array([(n - 1) / 2.0 * grid.spacing for n in grid.n]) * inner
+    for _ in range(count):
+        p = rng.uniform(-half, half)
+        d = _unit(rng.normal(size=3))
+        for _s in range(n_seg):
+            q = p + seg_len * d
+            box = _subbox(grid, np.minimum(p, q) - radius, np.maximum(p, q) + radius)
+            if box is not None:
+                idx, X = box
+                ab = q - p
+                t = np.clip(((X - p) @ ab) / float(ab @ ab), 0.0, 1.0)
+                dist2 = np.sum((X - (p + t[..., None] * ab)) ** 2, axis=-1)
+                _add_local(out, idx, (dist2 <= radius * radius).astype(np.float64), "max")
             p = q
             d = _unit(d + 0.5 * rng.normal(size=3))
     return out.ravel()
@@ -448,6 +500,25 @@ def config5(n: int = 128, B: int = 8) -> Problem:
     p = _finish("cfg5_batch8_planar256_128c", tr, grid, 50e6, 2048, coef, 1)
     p.meta["radii"] = [float(r) for r in radii]
     return p
+
+
+def config_lib(n: int = 200, angles=None, translations=None, U: int = 1, vessel_count: int = 24,
+               L: int = 2688) -> Problem:
+    """The LIB system's scale, synthesised (Sec. 2.6): a 10 mm cube on a 200^3
+    grid (50 um), the translate-rotate scan of ``lib_scan_array`` (64 elements x
+    12 angles x 15 translations = 11 520 cylinders; ``angles`` / ``translations``
+    select a subset), fs 62.5 MHz, L = 2688 stored samples; p0 = binary vessels
+    of radius 75 um (diameter capped at three voxels) along 24 random walks
+    (seed 21): ~0.3 % of the volume."""
+    grid = Grid.centred(n, 10e-3 / n)
+    full = lib_scan_array()
+    ang = range(12) if angles is None else angles
+    tra = range(15) if translations is None else translations
+    idx = [(a * 15 + t) * 64 + e for a in ang for t in tra for e in range(64)]
+    tr = full.subset(np.array(idx))
+    coef = vessels(grid, np.random.default_rng(21), vessel_count, 75e-6)
+    name = f"lib_{n}c_{tr.K}cyl" + ("" if U == 1 else f"_U{U}")
+    return _finish(name, tr, grid, 62.5e6, L, coef, 22, U=U)
 
 
 def small_case(shape: int = PLANAR, n: int = 6, K: int = 4, L: int = 160, fs: float = 40e6,
