@@ -200,19 +200,20 @@ void or_lut_set_size(int n)
     }
 }
 
-/* the cell [x_n, x_{n+1}] of the grid holding x and the position in it: the
-   inverse of Eq. LUT_sampling, t = 1 - (1 - x/(1 - eps))^(1/4), two square roots */
+/* the cell [x_n, x_{n+1}] of the grid holding x, found by inverting Eq.
+   LUT_sampling, t = 1 - (1 - x/(1 - eps))^(1/4) (two square roots), and the
+   linear weight of x in that cell, (x - x_n)/(x_{n+1} - x_n) */
 static void lut_locate(double x, int N, int* n, double* w)
 {
     double y = x / (1.0 - lut_eps);
     if (y > 1.0) y = 1.0;
     if (y < 0.0) y = 0.0;
     double t = 1.0 - sqrt(sqrt(1.0 - y));
-    double p = t * (N - 1);
-    int k = (int)floor(p);
+    int k = (int)floor(t * (N - 1));
     if (k > N - 2) k = N - 2;
+    double x0 = lut_node(k, N), x1 = lut_node(k + 1, N);
     *n = k;
-    *w = p - k;
+    *w = (fmin(x, 1.0 - lut_eps) - x0) / (x1 - x0);
 }
 
 /* bilinear interpolation of E~ and F~ at (s, nu) in [0, 1]^2 */

@@ -90,13 +90,12 @@ def test_singular_corner_is_finite_and_e_tends_to_one():
 
 
 def test_lookup_reproduces_the_nodes():
-    """At a node the interpolation returns the stored value.  Next to s = 1 the
-    grid inversion is ill-conditioned (1 - s carries the rounding of s, 1e-16,
-    on a gap of ~1e-12): there only to 1e-9."""
+    """At a node the interpolation returns the stored value (the weights are
+    linear in the coordinates, so a node found in either neighbouring cell
+    gives it)."""
     for i, j in [(3, 5), (500, 640), (998, 2), (10, 997), (999, 999), (999, 0), (900, 998)]:
         s, nu, E, _ = O.lut_entry(i, j)
-        tol = 1e-12 if s < 0.999 else 1e-9
-        assert O.lut_e(s, nu) == pytest.approx(E, rel=tol, abs=1e-15)
+        assert O.lut_e(s, nu) == pytest.approx(E, rel=1e-13, abs=1e-15)
 
 
 def _lookup_error(N, pts):
@@ -157,7 +156,7 @@ def test_lut_areas_converge_to_the_exact_areas():
         d = sum(np.abs(O.pair_areas_mode(tr, x, C, 0.0, 50e6, O.MODE_LUT, 1)[1] - e).sum()
                 for x, e in zip(xs, exact))
         errs.append(d / sum(np.abs(e).sum() for e in exact))
-    assert 0 < errs[-1] < 1e-4, errs
+    assert 0 < errs[-1] < 2e-4, errs
     assert errs[0] / errs[-1] > 6.0, errs
 
 
