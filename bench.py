@@ -143,15 +143,17 @@ def run_next(args, prob, kern, B, pairs, torch, dev, log):
     shape = 1 if 1 in set(int(v) for v in prob.tr.packed[:, 0]) else 0
     ex = (O.forward(prob, ksub=ks, kernel=(h, nf)), O.adjoint(prob, vsub=vs, kernel=(h, nf)))
     if shape == 1:
-        wall, f_ms, a_ms, ev, s, z = timed(prob, kern, "trapezoid", 1, max(1, min(3, args.steps)))
-        tz = (O.forward(prob, ksub=ks, mode=O.MODE_TRAPEZOID, kernel=(h, nf)),
-              O.adjoint(prob, vsub=vs, mode=O.MODE_TRAPEZOID, kernel=(h, nf)))
-        rows["trapezoid_fp32"] = {
-            "workload": prob.name, "ms_per_step": round(wall, 3), "ms_forward": round(f_ms, 3),
-            "ms_adjoint": round(a_ms, 3), "pairs_per_s": pairs / (wall * 1e-3), "area_evaluations": ev,
-            "rel_err_vs_exact_oracle": {"forward": rl2(s[:, ks], ex[0]), "adjoint": rl2(z[:, vs], ex[1])},
-            "rel_err_vs_oracle_trapezoid": {"forward": rl2(s[:, ks], tz[0]), "adjoint": rl2(z[:, vs], tz[1])}}
-        log(f"[bench] next trapezoid: {rows['trapezoid_fp32']}")
+        # the two cheaper cylinder I_l: chord of the level curve, lookup tables
+        for mode, omode in (("trapezoid", O.MODE_TRAPEZOID), ("lut", O.MODE_LUT)):
+            wall, f_ms, a_ms, ev, s, z = timed(prob, kern, mode, 1, max(1, min(3, args.steps)))
+            same = (O.forward(prob, ksub=ks, mode=omode, kernel=(h, nf)),
+                    O.adjoint(prob, vsub=vs, mode=omode, kernel=(h, nf)))
+            rows[f"{mode}_fp32"] = {
+                "workload": prob.name, "ms_per_step": round(wall, 3), "ms_forward": round(f_ms, 3),
+                "ms_adjoint": round(a_ms, 3), "pairs_per_s": pairs / (wall * 1e-3), "area_evaluations": ev,
+                "rel_err_vs_exact_oracle": {"forward": rl2(s[:, ks], ex[0]), "adjoint": rl2(z[:, vs], ex[1])},
+                f"rel_err_vs_oracle_{mode}": {"forward": rl2(s[:, ks], same[0]), "adjoint": rl2(z[:, vs], same[1])}}
+            log(f"[bench] next {mode}: {rows[f'{mode}_fp32']}")
     # the quadrature refined: error against the exact method and cost as Q grows
     q0 = tuple(prob.quad_n)
     for qn in (32, 64):
@@ -279,8 +281,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="one forward and one adjoint of the closed FP32 variant, nothing else")
     ap.add_argument("--next", action="store_true",
-                    help="also time the approximate variants (trapezoidal cylinder I_l on the workload; the "
-                         "coarse area grid on the 128^3 cylinder workload at U = 4) with their errors")
+                    help="also time the approximate variants (trapezoidal and lookup-table cylinder I_l and "
+                         "refined quadratures on the workload; the coarse area grid on the 128^3 cylinder "
+                         "workload at U = 4) with their errors")
     ap.add_argument("--lib", action="store_true",
                     help="only the LIB-scale rows (sparse forward at U = 61, dense A + A^T at U = 11 on a "
                          "sub-scan), printed as one JSON object instead of the benchmark line")

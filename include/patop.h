@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PATOP_ABI_VERSION 2
+#define PATOP_ABI_VERSION 3
 
 typedef enum {
     PAT_OK = 0,
@@ -61,8 +61,13 @@ enum { PAT_PLANAR = 0, PAT_CYLINDER = 1 };
 /* PAT_AREA_CLOSED: exact shell areas (Alg. 3 with Alg. 4).
  * PAT_AREA_QUADRATURE: surface points (Alg. 2, Eq. def_f_point).
  * PAT_AREA_TRAPEZOID: as PAT_AREA_CLOSED, but the cylinder's I_l by the chord of
- *   the level curve (Eq. trapezoid_Il, no elliptic integral); planar unchanged. */
-enum { PAT_AREA_CLOSED = 0, PAT_AREA_QUADRATURE = 1, PAT_AREA_TRAPEZOID = 2 };
+ *   the level curve (Eq. trapezoid_Il, no elliptic integral); planar unchanged.
+ * PAT_AREA_LUT: as PAT_AREA_CLOSED, but the cylinder's elliptic integrals read
+ *   from tables of E(arcsin s, nu) and F(arcsin s, nu) on the 1000 x 1000
+ *   power-law grid of Eq. LUT_sampling, interpolated bilinearly (Sec. 4.2, LUT
+ *   paragraph; nu > 1 by Eq. reciprocal_modulus).  The context keeps the 16 MB
+ *   FP64 table in device memory, built on the device by pat_set_geometry. */
+enum { PAT_AREA_CLOSED = 0, PAT_AREA_QUADRATURE = 1, PAT_AREA_TRAPEZOID = 2, PAT_AREA_LUT = 3 };
 enum { PAT_FP32 = 0, PAT_FP64 = 1 };
 enum { PAT_PHI_CONE = 0, PAT_PHI_WENDLAND2 = 1 };
 enum { PAT_EIR_GAUSS_COS = 0, PAT_EIR_SAMPLED = 1 };
@@ -119,7 +124,7 @@ typedef struct {
     double t0;             /* recording origin t_0 >= 0, s (Eq. def_operatorS) */
     int32_t L;             /* samples per transducer                   */
     int32_t U;             /* up-sampling factor of the fine grid      */
-    int32_t area_mode;     /* PAT_AREA_CLOSED, PAT_AREA_QUADRATURE or PAT_AREA_TRAPEZOID */
+    int32_t area_mode;     /* PAT_AREA_CLOSED, _QUADRATURE, _TRAPEZOID or _LUT        */
     int32_t quad_n1;       /* quadrature cells along the first surface coordinate  */
     int32_t quad_n2;       /* quadrature cells along the second surface coordinate */
     int32_t precision;     /* PAT_FP32 or PAT_FP64 (element type of device buffers) */
@@ -128,8 +133,8 @@ typedef struct {
     int32_t area_step;     /* coarse area grid of Remark 1: the area of each shell of
                               area_step fine bins (bins (j-1) area_step + 1 .. j area_step)
                               is evaluated once and split evenly over its bins;
-                              1 = every fine bin (exact); 1..U for the closed and
-                              trapezoid modes, 1 for quadrature                    */
+                              1 = every fine bin (exact); 1..U for the closed,
+                              trapezoid and table modes, 1 for quadrature          */
     int32_t reserved;      /* must be 0                                            */
 } pat_params;
 

@@ -16,8 +16,8 @@ STATUS_NAMES = ["PAT_OK", "PAT_E_ARG", "PAT_E_FRAME", "PAT_E_SHAPE", "PAT_E_SEPA
                 "PAT_E_STATE", "PAT_E_DEVICE", "PAT_E_OOM", "PAT_E_UNSUPPORTED"]
 
 PAT_PLANAR, PAT_CYLINDER = 0, 1
-PAT_AREA_CLOSED, PAT_AREA_QUADRATURE, PAT_AREA_TRAPEZOID = 0, 1, 2
-ABI_VERSION = 2
+PAT_AREA_CLOSED, PAT_AREA_QUADRATURE, PAT_AREA_TRAPEZOID, PAT_AREA_LUT = 0, 1, 2, 3
+ABI_VERSION = 3
 PAT_FP32, PAT_FP64 = 0, 1
 PAT_PHI_CONE, PAT_PHI_WENDLAND2 = 0, 1
 PAT_EIR_GAUSS_COS, PAT_EIR_SAMPLED = 0, 1

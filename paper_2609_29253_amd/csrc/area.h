@@ -39,9 +39,15 @@
 //   sin^2(u/2) = (s - v^2 - (R - rho)^2) / (4 R rho),
 //   1 - nu sin^2(u/2) = v^2 / (s - (R - rho)^2),
 // so arccos is never evaluated.
+//
+// Two cheaper I_l replace the Carlson evaluation (selected by IL): the chord of
+// the level curve (Eq. trapezoid_Il) and the lookup tables of E~, F~ (Sec. 4.2,
+// LUT paragraph), E(beta/2) - E(alpha/2) read off bilinearly at both end points.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "patop_internal.h"
 
 namespace patop {
 
@@ -52,6 +58,13 @@ namespace patop {
 __device__ __forceinline__ double rcp64(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 1/x with a second Newton step (full precision)
+__device__ __forceinline__ double rcp64_full(double x)
+{
+    double r = rcp64(x);
     return fma(r, fma(-x, r, 1.0), r);
 }
 
@@ -323,6 +336,14 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
 
 struct CyPair {
     double R, dm, mu, isq_mu;    // radius, |R - rho|, 4 R rho, 1/sqrt(mu) (0 when rho = 0)
+    const double2* lut;          // E~, F~ tables (lookup-table I_l only)
+};
+
+// how the cylinder's I_l is evaluated
+enum : int {
+    kIlExact = 0,       // Carlson, Eq. cyl_Il
+    kIlTrapezoid = 1,   // chord of the level curve, Eq. trapezoid_Il
+    kIlTable = 2,       // lookup tables of E~ and F~ (Sec. 4.2, LUT paragraph)
 };
 
 struct CyQuad {
@@ -421,9 +442,10 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // nu s^3 R_D(c^2, D^2, 1) / 3 (DLMF 19.25.9), with Carlson's duplication and
 // the series of DLMF 19.36.1-2 through degree 7.  Their truncation error is
 // ~eps^8 / 4 for eps = max |1 - x_i / A|, so the duplication stops once
-// eps < 1/35 (relative error ~1e-13).
-template <int NW>
-__device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu)
+// eps < 1/35 (relative error ~1e-13).  TABLE: stop at eps < 1e-4 instead
+// (truncation far below rounding) and also return F = s R_F(c^2, D^2, 1).
+template <int NW, bool TABLE = false>
+__device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu, double* f_out = nullptr)
 {
     double x = c * c, y = dl * dl, z = 1.0;
     double sx = fabs(c), sy = dl, sz = 1.0;
@@ -431,10 +453,11 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double AD = (x + y + 3.0 * z) * 0.2;
     double dev = fmax(fabs(AF - x), fmax(fabs(AF - y), fabs(AF - z)));
     dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
-    const double Qf = 35.0;
+    const double Qf = TABLE ? 1.0e4 : 35.0;
+    const int itmax = TABLE ? 40 : 12;
     double p4 = 1.0, sumD = 0.0;
 #pragma unroll 1
-    for (int it = 0; it < 12 && p4 * Qf * dev >= fmin(AF, AD); ++it) {
+    for (int it = 0; it < itmax && p4 * Qf * dev >= fmin(AF, AD); ++it) {
         double lam = fma(sx, sy, fma(sx, sz, sy * sz));
         sumD = fma(p4, rcp64(sz * (z + lam)), sumD);
         x = 0.25 * (x + lam);
@@ -465,7 +488,82 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
                  D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0) - D22 * D2 * (1.0 / 16.0) + D3 * D3 * (3.0 / 40.0) +
                  D2 * D4 * (3.0 / 20.0) + D22 * D3 * (45.0 / 272.0) - (D3 * D4 + D2 * D5) * (9.0 / 68.0);
     double rd = fma(p4 * ser * iAD, rAD, 3.0 * sumD);
+    if (TABLE) *f_out = s * rf;
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
+}
+
+// ---------------------------------------------------------------------------
+// lookup tables of E~(s, nu) = E(arcsin s, nu) and F~(s, nu) = F(arcsin s, nu)
+// ---------------------------------------------------------------------------
+// Both axes use the power-law grid of Eq. LUT_sampling, x_n = top (1 - (1 -
+// n/(N-1))^4), n = 0..N-1, top = 1 - 1e-16, which crowds the nodes towards the
+// logarithmic singularity of F at (1, 1).  Node (s_i, nu_j) holds {E~, F~} at
+// index j N + i, so the four corners of a cell are two 32-byte pairs.
+constexpr double kLutTop = 1.0 - 1e-16;
+constexpr double kLutInvTop = 1.0 / kLutTop;
+
+// node x_n; n / (N - 1) as the product with the rounded reciprocal plus one
+// correction step (the correctly rounded quotient)
+__device__ __forceinline__ double lut_node(int n)
+{
+    constexpr double inv = 1.0 / (double)(kLutN - 1);
+    const double dn = (double)n;
+    double q = dn * inv;
+    q = fma(fma(-q, (double)(kLutN - 1), dn), inv, q);
+    const double t = 1.0 - q;
+    return kLutTop * (1.0 - t * t * t * t);
+}
+
+// the grid cell [x_n, x_{n+1}] holding x, by the inverse of the grid map,
+// t = 1 - (1 - x/top)^(1/4) (two square roots), and the weight of x in it,
+// linear in the coordinate: (x - x_n) / (x_{n+1} - x_n)
+template <int NW>
+__device__ __forceinline__ void lut_cell(double x, int& n, double& w)
+{
+    const double y = fmin(fmax(x * kLutInvTop, 0.0), 1.0);
+    const double p = (1.0 - sqrt64<NW>(sqrt64<NW>(1.0 - y))) * (double)(kLutN - 1);
+    n = max(0, min((int)p, kLutN - 2));
+    const double x0 = lut_node(n), x1 = lut_node(n + 1);
+    const double d = x1 - x0;
+    w = (fmin(x, kLutTop) - x0) * (NW >= 2 ? rcp64_full(d) : rcp64(d));
+}
+
+// bilinear E~ and F~ at (s, nu), nu's cell (j, wn) given
+template <int NW>
+__device__ __forceinline__ void lut_ef(const double2* __restrict__ T, double s, int j, double wn, double& E,
+                                       double& F)
+{
+    int i;
+    double ws;
+    lut_cell<NW>(s, i, ws);
+    const double2* r = T + (j * kLutN + i);
+    const double2 a = r[0], b = r[1], c = r[kLutN], d = r[kLutN + 1];
+    const double e0 = fma(ws, b.x - a.x, a.x), e1 = fma(ws, d.x - c.x, c.x);
+    const double f0 = fma(ws, b.y - a.y, a.y), f1 = fma(ws, d.y - c.y, c.y);
+    E = fma(wn, e1 - e0, e0);
+    F = fma(wn, f1 - f0, f0);
+}
+
+// E(beta/2, nu) - E(alpha/2, nu) from the sines of the half angles by the
+// tables: E~ directly for nu <= 1; for nu > 1 the reciprocal-modulus form
+// (Eq. reciprocal_modulus) E(t, nu) = sqrt(nu) [E~(sqrt(nu) sin t, 1/nu) -
+// (1 - 1/nu) F~(sqrt(nu) sin t, 1/nu)], whose first argument stays <= 1 by
+// Lemma exact_integral.  Both end points share the nu cell.
+template <int NW>
+__device__ __forceinline__ double lut_de(const double2* __restrict__ T, double sa, double sb, double nu)
+{
+    const bool rec = nu > 1.0;
+    const double inu = NW >= 2 ? rcp64_full(nu) : rcp64(nu);
+    const double q = rec ? inu : nu;
+    const double g = rec ? sqrt64<NW>(nu) : 1.0;
+    const double cf = rec ? 1.0 - inu : 0.0;
+    int j;
+    double wn;
+    lut_cell<NW>(q, j, wn);
+    double Ea, Fa, Eb, Fb;
+    lut_ef<NW>(T, g * sa, j, wn, Ea, Fa);
+    lut_ef<NW>(T, g * sb, j, wn, Eb, Fb);
+    return g * fma(-cf, Fb - Fa, Eb - Ea);
 }
 
 // asin(u) for 0 <= u <= 0.05: odd Taylor series through u^11 (the first
@@ -482,8 +580,8 @@ __device__ __forceinline__ double asin_small(double u)
 }
 
 // Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I
-// (Eq. cyl_Il; with TRAP the chord of the level curve, Eq. trapezoid_Il)
-template <int NW, bool TRAP = false>
+// (Eq. cyl_Il; the chord of the level curve, Eq. trapezoid_Il, or the tables)
+template <int NW, int IL = kIlExact>
 __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
 {
     double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
@@ -496,7 +594,7 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
     if (!(cr > 0.0)) { E.I = 0.0; return; }
-    if (TRAP) {
+    if (IL == kIlTrapezoid) {
         // (beta - alpha)/2 (Psi(alpha) + Psi(beta)) with Psi = sqrt(K) Delta
         const double cs = fma(E.cb, E.ca, E.sb * E.sa);   // cos(beta/2 - alpha/2)
         const double sg = (cr <= 0.05 && cs > 0.0) ? asin_small(cr) : atan2(cr, cs);
@@ -504,6 +602,10 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
         return;
     }
     double nu = P.mu * isK * isK;
+    if (IL == kIlTable) {
+        E.I = 2.0 * K * isK * lut_de<NW>(P.lut, E.sa, E.sb, nu);
+        return;
+    }
     double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
     double idn = rcp64(den);
     double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
@@ -550,16 +652,16 @@ __device__ __forceinline__ void twice_angles(double cra, double dta, double crb,
     db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2(crb, dtb) : 0.0) : twice_atan_small(xb);
 }
 
-template <int NW, bool TRAP, class Sink>
+template <int NW, int IL, class Sink>
 __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, double r0, int wlo, int whi,
                                          double wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
     CyEdge E0, E1;
-    cy_edge<NW, TRAP>(q, P, r0 + (mb - 1), E0);
+    cy_edge<NW, IL>(q, P, r0 + (mb - 1), E0);
     for (int m = mb; m <= me; ++m) {
-        cy_edge<NW, TRAP>(q, P, r0 + m, E1);
+        cy_edge<NW, IL>(q, P, r0 + m, E1);
         double dal, dbe;
         twice_angles(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa),
                      fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb), dal, dbe);

@@ -44,6 +44,7 @@ struct pat_ctx {
     void* d_W = nullptr;
     double* d_z = nullptr;
     int32_t* d_sup = nullptr;       // support list [N], per-brick counts [nbricks], offsets [nbricks + 1]
+    double2* d_lut = nullptr;       // E~ / F~ tables [kLutN^2] (lookup-table I_l)
 };
 
 namespace {
@@ -75,7 +76,7 @@ void free_dev(pat_ctx* c)
 {
     void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, (void**)&c->d_G,
                      (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z,
-                     (void**)&c->d_sup};
+                     (void**)&c->d_sup, (void**)&c->d_lut};
     for (void** p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -218,7 +219,8 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!(p.sound_speed > 0.0) || !(p.fs > 0.0) || !(p.t0 >= 0.0) || !std::isfinite(p.t0) || p.L < 1 || p.U < 1 ||
         p.max_batch < 1 || p.flags != 0 || p.reserved != 0)
         return fail(c, PAT_E_ARG, "invalid sampling parameters");
-    if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE && p.area_mode != PAT_AREA_TRAPEZOID)
+    if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE && p.area_mode != PAT_AREA_TRAPEZOID &&
+        p.area_mode != PAT_AREA_LUT)
         return fail(c, PAT_E_ARG, "invalid area_mode");
     if (p.area_step < 1 || p.area_step > p.U || (p.area_mode == PAT_AREA_QUADRATURE && p.area_step != 1))
         return fail(c, PAT_E_ARG, "area_step must be in 1..U (1 for the quadrature)");
@@ -363,6 +365,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     const size_t wbytes = (size_t)p.max_batch * K * Mcount * rs;
     const size_t zbytes = (size_t)p.max_batch * N * sizeof(double);
     const size_t sbytes = surface ? ((size_t)N + 2 * (size_t)nbricks + 1) * sizeof(int32_t) : 0;
+    const size_t lbytes = p.area_mode == PAT_AREA_LUT ? sizeof(double2) * kLutN * kLutN : 0;
     auto dmalloc = [&](void** ptr, size_t bytes) -> bool {
         if (bytes == 0) bytes = 8;
         return hipMalloc(ptr, bytes) == hipSuccess;
@@ -370,14 +373,14 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!dmalloc((void**)&c->d_tr, sizeof(TrDev) * K) || !dmalloc((void**)&c->d_kperm, sizeof(int32_t) * K) ||
         !dmalloc((void**)&c->d_scale, sizeof(double) * Mcount) || !dmalloc((void**)&c->d_G, sizeof(double) * jcnt) ||
         !dmalloc((void**)&c->d_f, fbytes) || !dmalloc(&c->d_W, wbytes) || !dmalloc((void**)&c->d_z, zbytes) ||
-        (surface && !dmalloc((void**)&c->d_sup, sbytes)) ||
+        (surface && !dmalloc((void**)&c->d_sup, sbytes)) || (lbytes && !dmalloc((void**)&c->d_lut, lbytes)) ||
         (Q > 0 && (!dmalloc((void**)&c->d_qpts, sizeof(double) * qp.size()) ||
                    !dmalloc((void**)&c->d_qdA, sizeof(double) * K)))) {
         (void)hipGetLastError();
         free_dev(c);
         return fail(c, PAT_E_OOM, "device allocation failed");
     }
-    c->ws_bytes = fbytes + wbytes + zbytes + sbytes;
+    c->ws_bytes = fbytes + wbytes + zbytes + sbytes + lbytes;
     hipError_t e = hipSuccess;
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -390,6 +393,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         up(c->d_qpts, qp.data(), sizeof(double) * qp.size());
         up(c->d_qdA, qdA.data(), sizeof(double) * K);
     }
+    if (e == hipSuccess && lbytes) e = launch_lut_build(c->d_lut, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         std::string msg = std::string("upload failed: ") + hipGetErrorString(e);
@@ -421,6 +425,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     B.qpts = c->d_qpts;
     B.qdA = c->d_qdA;
     B.Q = Q;
+    B.lut = c->d_lut;
     Lp.ngroups = 0;
     int off = 0;
     for (int s = 0; s < 2; ++s) {

@@ -19,7 +19,8 @@ struct LaunchPlan {
     ShapeGroup groups[2];
     int ngroups;
     int nbricks;
-    int mode;               // 0 closed form, 1 quadrature, 2 closed form with the trapezoidal cylinder I_l
+    int mode;               // 0 closed form, 1 quadrature, 2 / 3 closed form with the trapezoidal /
+                            // lookup-table cylinder I_l
     bool fp64;
     int U, L;
     int jlo, jcnt;          // polyphase filter G[j], j = jlo .. jlo + jcnt - 1
@@ -37,6 +38,8 @@ struct LaunchPlan {
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
 // A restricted to the voxels where some volume's coefficient is nonzero (same result)
 hipError_t launch_forward_sparse(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
+// the E~ / F~ tables of the lookup-table I_l: kLutN^2 nodes {E~, F~}
+hipError_t launch_lut_build(double2* table, hipStream_t s);
 hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_t s);
 hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s);
 

@@ -83,16 +83,14 @@ __device__ __forceinline__ void brick_setup(const KParams& P, Brick& Bk)
     Bk.lo[2] = P.origin[2] + z0 * P.w; Bk.hi[2] = P.origin[2] + z1 * P.w;
 }
 
-// Sparse forward: work-group g takes entries 256 g .. 256 g + 255 of the support
-// list (nonzero voxels listed brick by brick, so they lie in a few neighbouring
-// bricks) and the box of those voxels.  Returns false for the whole work-group
-// when g is past the end of the list.
-__device__ __forceinline__ bool brick_setup_sparse(const KParams& P, Brick& Bk)
+// Sparse forward: group g is entries 256 g .. 256 g + 255 (< total) of the
+// support list (nonzero voxels listed brick by brick, so they lie in a few
+// neighbouring bricks), one per thread, with the box of those voxels.
+__device__ __forceinline__ void brick_setup_sparse(const KParams& P, int64_t g, int64_t total, Brick& Bk)
 {
     __shared__ int bmin[3], bmax[3];
-    const int64_t total = *P.sup_total;
-    const int64_t g0 = (int64_t)blockIdx.x * kThreads;
-    if (g0 >= total) return false;
+    const int64_t g0 = g * kThreads;
+    __syncthreads();   // the previous group's box has been read
     if (threadIdx.x < 3) { bmin[threadIdx.x] = 0x7fffffff; bmax[threadIdx.x] = -1; }
     __syncthreads();
     const int64_t e = g0 + threadIdx.x;
@@ -111,7 +109,6 @@ __device__ __forceinline__ bool brick_setup_sparse(const KParams& P, Brick& Bk)
         Bk.lo[a] = P.origin[a] + bmin[a] * P.w;
         Bk.hi[a] = P.origin[a] + bmax[a] * P.w;
     }
-    return true;
 }
 
 // bins that any voxel of the brick can reach on transducer T (bounding sphere)
@@ -190,7 +187,7 @@ template <class AT>
 struct PlanarPair {
     WInt U, V;
     double z2;
-    __device__ __forceinline__ void bind(double*) {}
+    __device__ __forceinline__ void bind(double*, const double2*) {}
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
         double L1 = T.p[0], L2 = T.p[1];
@@ -239,13 +236,20 @@ __device__ __forceinline__ double wrap_pi(double u)
 // live through every sweep and pushed to scratch memory at three waves per SIMD.
 constexpr int kBoxSlots = 8;
 
-template <int NW, bool TRAP>
+// MERGE of the folded intervals holds for every I_l that is a difference of a
+// function of the end points (exact, tables); not for the chord.
+template <int NW, int IL>
 struct CylinderPair {
+    static constexpr bool kMerge = IL != kIlTrapezoid;
     CyPair P;
     double* box;             // this thread's column of the LDS box table
     int list, nq;            // non-empty quadrants (2 bits each, in sweep order) and their number
     int wbits;               // quadrant weights: bits 0/1 the U intervals, 2/3 the V intervals (set = 2)
-    __device__ __forceinline__ void bind(double* table) { box = table + threadIdx.x; }
+    __device__ __forceinline__ void bind(double* table, const double2* lut)
+    {
+        box = table + threadIdx.x;
+        P.lut = lut;
+    }
     __device__ __forceinline__ void setup(const TrDev& T, const double x[3], double)
     {
         WInt U, V;
@@ -259,10 +263,10 @@ struct CylinderPair {
         double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
         // Eq. folded_intervals (merged where the areas are exact, see split_at_zero)
         if (u1 < 0.0 && 0.0 < u2) {
-            split_at_zero<!TRAP>(-u1, u2, U);
+            split_at_zero<kMerge>(-u1, u2, U);
         } else if (u2 < u1) {
             // [u1, pi] and [-u2, pi]
-            if (TRAP) {
+            if (!kMerge) {
                 U.lo[0] = u1;  U.hi[0] = M_PI; U.w[0] = 1.0f;
                 U.lo[1] = -u2; U.hi[1] = M_PI; U.w[1] = 1.0f;
             } else {
@@ -276,7 +280,7 @@ struct CylinderPair {
         } else {
             U.lo[0] = -u2; U.hi[0] = -u1; U.w[0] = 1.0f; U.n = 1;
         }
-        fold_line<!TRAP>(-Lz - x[2], Lz - x[2], V);
+        fold_line<kMerge>(-Lz - x[2], Lz - x[2], V);
         list = 0;
         nq = 0;
 #pragma unroll
@@ -311,7 +315,7 @@ struct CylinderPair {
             quadrant((list >> (2 * t)) & 3, a, b, c, d, w);
             CyQuad q;
             cy_setup(q, P, a, b, c, d, r0);
-            cy_sweep<NW, TRAP>(q, P, r0, wlo, whi, w, sink);
+            cy_sweep<NW, IL>(q, P, r0, wlo, whi, w, sink);
         }
     }
 };
@@ -322,29 +326,24 @@ struct CylinderPair {
 template <class Real> struct CylNewton { static constexpr int value = 2; };
 template <> struct CylNewton<float> { static constexpr int value = 1; };
 
-// TRAP: the cylinder's I_l by the trapezoid (Eq. trapezoid_Il); planar I_l is exact either way
-template <int SHAPE, class AT, class Real, bool TRAP> struct PairOf;
-template <class AT, class Real, bool TRAP> struct PairOf<0, AT, Real, TRAP> { using type = PlanarPair<AT>; };
-template <class AT, class Real, bool TRAP> struct PairOf<1, AT, Real, TRAP> {
-    using type = CylinderPair<CylNewton<Real>::value, TRAP>;
+// IL: how the cylinder's I_l is evaluated (kIlExact, kIlTrapezoid, kIlTable);
+// the planar I_l is exact either way
+template <int SHAPE, class AT, class Real, int IL> struct PairOf;
+template <class AT, class Real, int IL> struct PairOf<0, AT, Real, IL> { using type = PlanarPair<AT>; };
+template <class AT, class Real, int IL> struct PairOf<1, AT, Real, IL> {
+    using type = CylinderPair<CylNewton<Real>::value, IL>;
 };
 
 // ---------------------------------------------------------------------------
 // forward, closed-form areas
 // ---------------------------------------------------------------------------
 
-template <int SHAPE, class AT, int NB, class Real, bool TRAP, bool SPARSE>
-__global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
-                                                          double* __restrict__ f)
+// one brick (or group of support voxels) against transducers kperm[kbeg .. kend)
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int kbeg, int kend,
+                                          const Real* __restrict__ coef, double* __restrict__ f, double* hist,
+                                          double* box)
 {
-    extern __shared__ double hist[];   // [NB][kHist]
-    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
-    Brick Bk;
-    if (SPARSE) {
-        if (!brick_setup_sparse(P, Bk)) return;
-    } else {
-        brick_setup(P, Bk);
-    }
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -353,14 +352,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
         nz |= p0[b] != 0.0;
     }
     if (!__syncthreads_or(nz)) return;
-    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
         int wlo, whi;
         // the pair's geometry once per transducer; the transducer record is not
         // needed afterwards
-        typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
-        pair.bind(box);
+        typename PairOf<SHAPE, AT, Real, IL>::type pair;
+        pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
             brick_window(P, Bk, T, wlo, whi);
@@ -402,11 +400,43 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
     }
 }
 
+// sparse forward: transducers per work item and work-groups of the strided grid
+// (16 waves per CU at 256 CUs)
+constexpr int kSparseChunk = 16;
+constexpr int kSparseGrid = 4096;
+
+// Dense: work-group (brick, chunk of transducers).  SPARSE: the work items
+// (group of 256 support entries, chunk of P.kchunk transducers) are strided over
+// a fixed grid, since the number of groups is known on the device only.
+template <int SHAPE, class AT, int NB, class Real, int IL, bool SPARSE>
+__global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
+                                                          double* __restrict__ f)
+{
+    extern __shared__ double hist[];   // [NB][kHist]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
+    if (!SPARSE) {
+        Brick Bk;
+        brick_setup(P, Bk);
+        const int kbeg = blockIdx.y * P.kchunk;
+        fwd_brick<SHAPE, AT, NB, Real, IL>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+        return;
+    }
+    const int64_t total = *P.sup_total;
+    const int64_t nchunks = (P.nk + P.kchunk - 1) / P.kchunk;
+    const int64_t items = (total + kThreads - 1) / kThreads * nchunks;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        Brick Bk;
+        brick_setup_sparse(P, it / nchunks, total, Bk);
+        const int kbeg = (int)(it % nchunks) * P.kchunk;
+        fwd_brick<SHAPE, AT, NB, Real, IL>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // adjoint, closed-form areas
 // ---------------------------------------------------------------------------
 
-template <int SHAPE, class AT, int NB, class Real, bool TRAP>
+template <int SHAPE, class AT, int NB, class Real, int IL>
 __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Real* __restrict__ W,
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
@@ -423,8 +453,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
         int wlo, whi;
-        typename PairOf<SHAPE, AT, Real, TRAP>::type pair;
-        pair.bind(box);
+        typename PairOf<SHAPE, AT, Real, IL>::type pair;
+        pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
             brick_window(P, Bk, T, wlo, whi);
@@ -641,8 +671,8 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
             const int lo = (int)P.Jlo, hi = (int)P.Jhi;
             int nb = 0;
             auto sink = [&](int, auto) { ++nb; };
-            typename PairOf<SHAPE, double, double, false>::type pair;
-            pair.bind(box);
+            typename PairOf<SHAPE, double, double, kIlExact>::type pair;
+            pair.bind(box, nullptr);
             pair.setup(T, x, P.r0);
             pair.sweep(lo, hi, sink, P.r0);
             evals += nb;
@@ -772,36 +802,72 @@ __global__ void k_adjw(const Real* __restrict__ y, const double* __restrict__ sc
 }
 
 // ---------------------------------------------------------------------------
+// E~ / F~ tables of the lookup-table I_l, one node per thread
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_lut_build(double2* __restrict__ T)
+{
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= kLutN * kLutN) return;
+    const double s = lut_node(id % kLutN), nu = lut_node(id / kLutN);
+    double E = 0.0, F = 0.0;
+    if (s > 0.0) {
+        const double c = sqrt64<2>((1.0 - s) * (1.0 + s));   // cos(arcsin s)
+        const double dl = sqrt64<2>(fma(-nu * s, s, 1.0));    // Delta(arcsin s)
+        E = ellip_e_scd<2, true>(s, c, dl, nu, &F);
+    }
+    T[id] = make_double2(E, F);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
 namespace {
 
-template <int SHAPE, class AT, class Real, bool TRAP, bool SPARSE = false>
+template <int SHAPE, class AT, class Real, int IL, bool SPARSE = false>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
     size_t sh = (size_t)nb * kHist * sizeof(double);
     switch (nb) {
-    case 1: k_fwd_closed<SHAPE, AT, 1, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 2: k_fwd_closed<SHAPE, AT, 2, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 4: k_fwd_closed<SHAPE, AT, 4, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    default: k_fwd_closed<SHAPE, AT, 8, Real, TRAP, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 4: k_fwd_closed<SHAPE, AT, 4, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    default: k_fwd_closed<SHAPE, AT, 8, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     }
     return hipGetLastError();
 }
 
-template <int SHAPE, class AT, class Real, bool TRAP>
+template <int SHAPE, class AT, class Real, int IL>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
     size_t sh = (size_t)nb * kHist * sizeof(Real);
     switch (nb) {
-    case 1: k_adj_closed<SHAPE, AT, 1, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 2: k_adj_closed<SHAPE, AT, 2, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 4: k_adj_closed<SHAPE, AT, 4, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    default: k_adj_closed<SHAPE, AT, 8, Real, TRAP><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_closed<SHAPE, AT, 4, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_closed<SHAPE, AT, 8, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     }
     return hipGetLastError();
+}
+
+// cylinder launches by I_l variant: area mode 0 exact, 2 trapezoid, 3 tables
+template <class Real, bool SPARSE>
+hipError_t fwd_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
+{
+    if (mode == 2) return fwd_closed_nb<1, double, Real, kIlTrapezoid, SPARSE>(nb, grid, P, coef, f, s);
+    if (mode == 3) return fwd_closed_nb<1, double, Real, kIlTable, SPARSE>(nb, grid, P, coef, f, s);
+    return fwd_closed_nb<1, double, Real, kIlExact, SPARSE>(nb, grid, P, coef, f, s);
+}
+
+template <class Real>
+hipError_t adj_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64,
+                   int direct, hipStream_t s)
+{
+    if (mode == 2) return adj_closed_nb<1, double, Real, kIlTrapezoid>(nb, grid, P, W, out, z64, direct, s);
+    if (mode == 3) return adj_closed_nb<1, double, Real, kIlTable>(nb, grid, P, W, out, z64, direct, s);
+    return adj_closed_nb<1, double, Real, kIlExact>(nb, grid, P, W, out, z64, direct, s);
 }
 
 template <class AT, class Real>
@@ -871,14 +937,14 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
             if (sparse) {
                 P.sup_list = L.sup_list;
                 P.sup_total = L.sup_off + L.nbricks;
+                P.kchunk = kSparseChunk;
+                grid = dim3(kSparseGrid, 1);
             }
             if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
-            else if (sparse && G.shape == 0) e = fwd_closed_nb<0, Real, Real, false, true>(nb, grid, P, cb, fb, s);
-            else if (sparse && L.mode == 2) e = fwd_closed_nb<1, double, Real, true, true>(nb, grid, P, cb, fb, s);
-            else if (sparse) e = fwd_closed_nb<1, double, Real, false, true>(nb, grid, P, cb, fb, s);
-            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, false>(nb, grid, P, cb, fb, s);
-            else if (L.mode == 2) e = fwd_closed_nb<1, double, Real, true>(nb, grid, P, cb, fb, s);
-            else e = fwd_closed_nb<1, double, Real, false>(nb, grid, P, cb, fb, s);
+            else if (sparse && G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact, true>(nb, grid, P, cb, fb, s);
+            else if (sparse) e = fwd_cyl<Real, true>(L.mode, nb, grid, P, cb, fb, s);
+            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact>(nb, grid, P, cb, fb, s);
+            else e = fwd_cyl<Real, false>(L.mode, nb, grid, P, cb, fb, s);
             if (e != hipSuccess) return e;
         }
         b0 += nb;
@@ -918,9 +984,8 @@ hipError_t adjoint_t(const LaunchPlan& L, const Real* sig, Real* coef, int B, hi
             Real* ob = coef + (int64_t)b0 * P.N;
             double* zb = L.z64 + (int64_t)b0 * P.N;
             if (L.mode == 1) e = adj_quad_nb<Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
-            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real, false>(nb, grid, P, Wb, ob, zb, direct, s);
-            else if (L.mode == 2) e = adj_closed_nb<1, double, Real, true>(nb, grid, P, Wb, ob, zb, direct, s);
-            else e = adj_closed_nb<1, double, Real, false>(nb, grid, P, Wb, ob, zb, direct, s);
+            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real, kIlExact>(nb, grid, P, Wb, ob, zb, direct, s);
+            else e = adj_cyl<Real>(L.mode, nb, grid, P, Wb, ob, zb, direct, s);
             if (e != hipSuccess) return e;
         }
         b0 += nb;
@@ -952,6 +1017,12 @@ hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int 
 {
     if (L.fp64) return forward_t<double>(L, (const double*)coef, (double*)sig, B, s, false);
     return forward_t<float>(L, (const float*)coef, (float*)sig, B, s, false);
+}
+
+hipError_t launch_lut_build(double2* table, hipStream_t s)
+{
+    k_lut_build<<<(kLutN * kLutN + 255) / 256, 256, 0, s>>>(table);
+    return hipGetLastError();
 }
 
 hipError_t launch_forward_sparse(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s)

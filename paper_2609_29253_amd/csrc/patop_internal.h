@@ -21,6 +21,7 @@ static_assert(kBrickX * kBrickY * kBrickZ == kThreads, "one voxel per thread");
 static_assert(kBrickX == 8 && kBrickY == 8 && kBrickZ == 4, "four 4 x 4 x 4 wave sub-cubes per brick");
 constexpr int kHist = 1024;        // fine bins per LDS window pass
 constexpr int kMaxNB = 8;          // volumes per launch
+constexpr int kLutN = 1000;        // nodes per axis of the E~ / F~ tables (lookup-table I_l)
 
 // One transducer, device side (all lengths in dr units).
 struct TrDev {
@@ -53,6 +54,8 @@ struct KParams {
     // support of the coefficients (forward restricted to nonzero voxels)
     const int32_t* sup_list;    // voxel indices, brick by brick
     const int32_t* sup_total;   // [1] number of entries
+    // lookup-table I_l: {E~, F~} on the power-law grid, node (i, j) at j N + i
+    const double2* lut;
     // quadrature
     const double* qpts;     // [K][Q][3] global point coordinates
     const double* qdA;      // [K] cell area (dr^2 units)

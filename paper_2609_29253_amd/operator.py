@@ -76,7 +76,8 @@ class PatOperator:
         p = L.Params()
         p.sound_speed, p.fs, p.t0 = float(sound_speed), float(fs), float(t0)
         p.L, p.U = self.L, int(U)
-        modes = {"closed": L.PAT_AREA_CLOSED, "quadrature": L.PAT_AREA_QUADRATURE, "trapezoid": L.PAT_AREA_TRAPEZOID}
+        modes = {"closed": L.PAT_AREA_CLOSED, "quadrature": L.PAT_AREA_QUADRATURE,
+                 "trapezoid": L.PAT_AREA_TRAPEZOID, "lut": L.PAT_AREA_LUT}
         if mode not in modes:
             raise ValueError(f"mode must be one of {sorted(modes)}")
         p.area_mode = modes[mode]

@@ -25,7 +25,10 @@ def lib_small():
     return P.config_lib(n=64, angles=[0, 5, 9], translations=[2, 7, 12], vessel_count=10, L=1400)
 
 
-@pytest.mark.parametrize("mode", ["closed", "trapezoid"])
+OMODE = {"closed": O.MODE_SURFACE, "trapezoid": O.MODE_TRAPEZOID, "lut": O.MODE_LUT}
+
+
+@pytest.mark.parametrize("mode", ["closed", "trapezoid", "lut"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_sparse_forward_matches_full_and_oracle(gpu, prec, mode):
     from paper_2609_29253_amd.operator import PatOperator
@@ -39,7 +42,7 @@ def test_sparse_forward_matches_full_and_oracle(gpu, prec, mode):
     s_sp = op.forward(c, sparse=True).double().cpu().numpy()
     op.close()
     ks = np.arange(0, p.K, 37, dtype=np.int32)
-    s_ref = O.forward(p, ksub=ks, mode=O.MODE_SURFACE if mode == "closed" else O.MODE_TRAPEZOID)
+    s_ref = O.forward(p, ksub=ks, mode=OMODE[mode])
     e_self, e_ref = rel_l2(s_sp, s_full), rel_l2(s_sp[:, ks], s_ref)
     print(f"  sparse vs full {e_self:.3e}   sparse vs oracle {e_ref:.3e}", flush=True)
     assert e_self < SELF[prec] and e_ref < TOL[prec]

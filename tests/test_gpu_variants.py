@@ -1,7 +1,8 @@
 """The approximate surface variants on the GPU against the oracle's own
 versions of them, element by element through the C ABI: the coarse area grid
 of Remark 1 (each shell of `area_step` fine bins evaluated once and split
-evenly) and the trapezoidal cylinder I_l (Eq. trapezoid_Il).
+evenly), the trapezoidal cylinder I_l (Eq. trapezoid_Il) and the lookup-table
+I_l (Sec. 4.2, LUT paragraph; the device builds its own tables).
 
 Same bar as the exact method: FP32 1e-5 and FP64 1e-11 relative L2, since the
 HIP path and the oracle evaluate the same approximation.  Shapes cover several
@@ -20,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-5, "fp64": 1e-11}
 DT = {"fp32": torch.float32, "fp64": torch.float64}
-OMODE = {"closed": O.MODE_SURFACE, "trapezoid": O.MODE_TRAPEZOID}
+OMODE = {"closed": O.MODE_SURFACE, "trapezoid": O.MODE_TRAPEZOID, "lut": O.MODE_LUT}
 
 
 def run_gpu(prob, mode, prec, step):
@@ -47,6 +48,11 @@ CASES = [
     (P.PLANAR, 3, 3, 2, 11, 4, 200, "closed"),
     (P.PLANAR, 5, 2, 1, 9, 4, 200, "closed"),
     (P.PLANAR, 2, 2, 1, 9, 3, 200, "trapezoid"),
+    (P.CYLINDER, 1, 1, 1, 11, 4, 260, "lut"),
+    (P.CYLINDER, 2, 1, 3, 9, 4, 260, "lut"),
+    (P.CYLINDER, 4, 2, 2, 9, 3, 260, "lut"),
+    (P.CYLINDER, 3, 3, 1, 11, 4, 260, "lut"),
+    (P.PLANAR, 2, 1, 1, 9, 3, 200, "lut"),
 ]
 
 
@@ -67,6 +73,22 @@ def test_variant_parity(gpu, case, prec):
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
     print(f"  forward rel L2 {es:.3e}  adjoint rel L2 {ez:.3e}  area evaluations {evals:.0f}", flush=True)
     assert es < TOL[prec] and ez < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_lut_reaches_the_nu_above_one_branch(gpu, prec):
+    """Voxels on both sides of the focal line of a strongly focused element, so
+    that nu = 4 R rho / (r^2 - (R - rho)^2) spans both table branches
+    (nu <= 1 directly, nu > 1 by the reciprocal modulus), checked on the oracle."""
+    p = P.small_case(P.CYLINDER, n=11, K=6, U=2, B=1, L=300, seed=8, spacing=0.15e-3, radius=6e-3)
+    s_ref = O.forward(p, mode=O.MODE_LUT)
+    z_ref = O.adjoint(p, mode=O.MODE_LUT)
+    s, z, _ = run_gpu(p, "lut", prec, 1)
+    es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
+    ex = rel_l2(s, O.forward(p))
+    print(f"lut {prec}: forward {es:.3e} adjoint {ez:.3e}; method error vs exact {ex:.3e}", flush=True)
+    assert es < TOL[prec] and ez < TOL[prec]
+    assert ex < 1e-3
 
 
 def test_coarse_grid_cuts_evaluations(gpu):
