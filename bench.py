@@ -191,7 +191,9 @@ def run_lib(torch, dev, log):
     area per fine bin, in FP64: the paper's exact reference application.  (2)
     The dense A + A^T at U = 11, area per native sample and per fine bin, on a
     sub-scan of one angle x 5 translations (320 cylinders), scaled by K to the
-    whole scan: the operator of the paper's reconstruction.  Errors against the
+    whole scan: the operator of the paper's reconstruction.  (The forward skips
+    the all-zero bricks of the sparse phantom by itself; the adjoint covers every
+    voxel.)  Errors against the
     oracle on a few transducers / voxels."""
     import numpy as np
     import oracle as O
@@ -220,7 +222,6 @@ def run_lib(torch, dev, log):
     op = PatOperator.from_problem(p, mode="closed", precision="fp64")
     coef = torch.tensor(p.coef, dtype=torch.float64, device=dev)
     ms, s = events(lambda: op.forward(coef, sparse=True))
-    evals = op.query(7)
     ks = np.array([1234, 7777], dtype=np.int32)
     got = s[:, torch.tensor(ks, device=dev).long()].cpu().numpy()
     ws = op.query(5)
@@ -232,7 +233,7 @@ def run_lib(torch, dev, log):
     pairs = float(nz) * p.K
     rows["lib_sparse_forward_U61_step1_fp64"] = {
         "workload": p.name, "U": p.U, "area_step": 1, "nonzero_voxels": nz, "ms_forward": round(ms, 3),
-        "pairs_per_s": pairs / (ms * 1e-3), "area_evaluations": evals, "workspace_bytes": ws,
+        "pairs": pairs, "pairs_per_s": pairs / (ms * 1e-3), "workspace_bytes": ws,
         "paper_seconds": 7200.0, "paper_pairs_per_s": 3.8e4,
         "rel_err_vs_oracle": {"forward_transducers": ks.tolist(), "forward": rl2(got, ref)}}
     log(f"[bench] lib sparse forward: {rows['lib_sparse_forward_U61_step1_fp64']}")
@@ -280,6 +281,8 @@ def main():
                     help="copy a 256 MiB device buffer first (reference kernel for HBM counters)")
     ap.add_argument("--profile-only", action="store_true",
                     help="one forward and one adjoint of the closed FP32 variant, nothing else")
+    ap.add_argument("--profile-mode", default="closed", choices=["closed", "quadrature", "trapezoid", "lut"],
+                    help="area method of --profile-only")
     ap.add_argument("--next", action="store_true",
                     help="also time the approximate variants (trapezoidal and lookup-table cylinder I_l and "
                          "refined quadratures on the workload; the coarse area grid on the 128^3 cylinder "
@@ -340,13 +343,13 @@ def main():
         return out
 
     if args.profile_only:
-        op = PatOperator.from_problem(prob, mode="closed", precision="fp32", max_batch=B, kernel=kern)
+        op = PatOperator.from_problem(prob, mode=args.profile_mode, precision="fp32", max_batch=B, kernel=kern)
         coef = torch.tensor(prob.coef, dtype=torch.float32, device=dev)
         y = torch.tensor(prob.y, dtype=torch.float32, device=dev)
         op.forward(coef)
         op.adjoint(y)
         torch.cuda.synchronize()
-        log(f"[bench] profile run done: one A and one A^T of {prob.name}")
+        log(f"[bench] profile run done: one A and one A^T of {prob.name} ({args.profile_mode})")
         op.close()
         return
     main_res = run_variant("closed", "fp32", args.steps, args.warmup)
