@@ -366,7 +366,7 @@ def main():
     area_dtype = "f64" if shape == 1 else "f32"
     achieved = flops / (dom_ms * 1e-3) / 1e12
     peak = PEAKS[area_dtype] / 1e12
-    dom_full = f"{dom_name}<{shape}, double, 1, float, false>" if shape == 1 else dom_name
+    dom_full = f"{dom_name}<{shape}, double, 1, float, 0, false>" if shape == 1 else dom_name
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_full, prob.name),
                 "kernel": dom_name,
