@@ -43,7 +43,8 @@ struct pat_ctx {
     double* d_f = nullptr;
     void* d_W = nullptr;
     double* d_z = nullptr;
-    int32_t* d_sup = nullptr;       // support list [N], per-brick counts [nbricks], offsets [nbricks + 1]
+    int32_t* d_sup = nullptr;       // support list [N], per-brick counts [nbricks], offsets [nbricks + 1],
+                                    // brick order [nbricks]
     double2* d_lut = nullptr;       // E~ / F~ tables [kLutN^2] (lookup-table I_l)
 };
 
@@ -364,7 +365,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     const size_t fbytes = (size_t)p.max_batch * K * Mcount * sizeof(double);
     const size_t wbytes = (size_t)p.max_batch * K * Mcount * rs;
     const size_t zbytes = (size_t)p.max_batch * N * sizeof(double);
-    const size_t sbytes = surface ? ((size_t)N + 2 * (size_t)nbricks + 1) * sizeof(int32_t) : 0;
+    const size_t sbytes = surface ? ((size_t)N + 3 * (size_t)nbricks + 1) * sizeof(int32_t) : 0;
     const size_t lbytes = p.area_mode == PAT_AREA_LUT ? sizeof(double2) * kLutN * kLutN : 0;
     auto dmalloc = [&](void** ptr, size_t bytes) -> bool {
         if (bytes == 0) bytes = 8;
@@ -389,6 +390,22 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     up(c->d_kperm, perm.data(), sizeof(int32_t) * K);
     up(c->d_scale, scale.data(), sizeof(double) * Mcount);
     up(c->d_G, G.data(), sizeof(double) * jcnt);
+    if (surface) {
+        // bricks in Morton order of (bx, by, bz): the sparse forward's groups of
+        // consecutive support entries then stay spatially compact
+        std::vector<std::pair<uint64_t, int32_t>> mk(nbricks);
+        for (int b = 0; b < nbricks; ++b) {
+            const uint64_t c3[3] = {(uint64_t)(b % nbx), (uint64_t)((b / nbx) % nby), (uint64_t)(b / (nbx * nby))};
+            uint64_t key = 0;
+            for (int bit = 0; bit < 21; ++bit)
+                for (int a = 0; a < 3; ++a) key |= ((c3[a] >> bit) & 1ull) << (3 * bit + a);
+            mk[b] = {key, b};
+        }
+        std::sort(mk.begin(), mk.end());
+        std::vector<int32_t> order(nbricks);
+        for (int b = 0; b < nbricks; ++b) order[b] = mk[b].second;
+        up(c->d_sup + N + 2 * (size_t)nbricks + 1, order.data(), sizeof(int32_t) * nbricks);
+    }
     if (Q > 0) {
         up(c->d_qpts, qp.data(), sizeof(double) * qp.size());
         up(c->d_qdA, qdA.data(), sizeof(double) * K);
@@ -456,6 +473,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         Lp.sup_list = c->d_sup;
         Lp.sup_cnt = c->d_sup + N;
         Lp.sup_off = c->d_sup + N + nbricks;
+        Lp.sup_order = c->d_sup + N + 2 * nbricks + 1;
     }
 
     c->K = K;

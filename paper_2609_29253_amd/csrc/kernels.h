@@ -31,8 +31,9 @@ struct LaunchPlan {
     void* W;                // [max_batch][K][Mcount] adjoint workspace (float or double)
     double* z64;            // [max_batch][N] adjoint FP64 partial sums
     int32_t* sup_list;      // [N] support of the coefficients (sparse forward)
-    int32_t* sup_cnt;       // [nbricks] nonzero voxels per brick
+    int32_t* sup_cnt;       // [nbricks] nonzero voxels per brick (in sup_order)
     int32_t* sup_off;       // [nbricks + 1] their exclusive prefix sums (last entry: total)
+    const int32_t* sup_order;   // [nbricks] brick indices in Morton order (the list's brick order)
 };
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);

@@ -61,9 +61,8 @@ struct Brick {
     double lo[3], hi[3];   // axis-aligned box of the brick's voxel centres (global)
 };
 
-__device__ __forceinline__ void brick_setup(const KParams& P, Brick& Bk)
+__device__ __forceinline__ void brick_setup(const KParams& P, int bid, Brick& Bk)
 {
-    const int bid = blockIdx.x;
     const int bxi = bid % P.nbx, byi = (bid / P.nbx) % P.nby, bzi = bid / (P.nbx * P.nby);
     const int x0 = bxi * kBrickX, y0 = byi * kBrickY, z0 = bzi * kBrickZ;
     // each wave owns a 4 x 4 x 4 sub-cube of the brick: the most compact set of
@@ -344,6 +343,7 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
                                           const Real* __restrict__ coef, double* __restrict__ f, double* hist,
                                           double* box)
 {
+    constexpr int HB = kHistTotal / NB;   // shells per pass
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -366,17 +366,17 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
             frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
             pair.setup(T, x, P.r0);
         }
-        for (int plo = wlo; plo <= whi; plo += kHist) {
-            const int phi = min(whi, plo + kHist - 1);
+        for (int plo = wlo; plo <= whi; plo += HB) {
+            const int phi = min(whi, plo + HB - 1);
             const int wn = phi - plo + 1;
             for (int i = threadIdx.x; i < wn; i += kThreads)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) hist[b * kHist + i] = 0.0;
+                for (int b = 0; b < NB; ++b) hist[b * HB + i] = 0.0;
             __syncthreads();
             if (nz) {
                 auto sink = [&](int m, auto area) {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (m - plo)], p0[b] * (double)area);
+                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * HB + (m - plo)], p0[b] * (double)area);
                 };
                 pair.sweep(plo, phi, sink, P.r0);
             }
@@ -391,7 +391,7 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
                 if (m < P.Mlo || m > Mhi) continue;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    double v = hist[b * kHist + jj];
+                    double v = hist[b * HB + jj];
                     if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + (m - P.Mlo)], v * S);
                 }
             }
@@ -408,15 +408,23 @@ constexpr int kSparseGrid = 4096;
 // Dense: work-group (brick, chunk of transducers).  SPARSE: the work items
 // (group of 256 support entries, chunk of P.kchunk transducers) are strided over
 // a fixed grid, since the number of groups is known on the device only.
+// waves per SIMD the closed-form kernels are built for: three, whose 168 VGPRs
+// hold the FP64 cylinder sweep with few spills.  The planar sweep in FP64 for
+// four or eight volumes spills 300 bytes per lane at three and runs faster at
+// two (1.75x for the adjoint of eight volumes); for one volume three is faster
+// despite its spills (9 %).
+template <int SHAPE, class AT, int NB>
+constexpr int closed_waves() { return SHAPE == 0 && sizeof(AT) == 8 && NB >= 4 ? 2 : 3; }
+
 template <int SHAPE, class AT, int NB, class Real, int IL, bool SPARSE>
-__global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
+__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
-    extern __shared__ double hist[];   // [NB][kHist]
+    extern __shared__ double hist[];   // [NB][kHistTotal / NB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     if (!SPARSE) {
         Brick Bk;
-        brick_setup(P, Bk);
+        brick_setup(P, blockIdx.x, Bk);
         const int kbeg = blockIdx.y * P.kchunk;
         fwd_brick<SHAPE, AT, NB, Real, IL>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
         return;
@@ -437,15 +445,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_fwd_closed(KParams P, const Rea
 // ---------------------------------------------------------------------------
 
 template <int SHAPE, class AT, int NB, class Real, int IL>
-__global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Real* __restrict__ W,
+__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_adj_closed(KParams P, const Real* __restrict__ W,
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
 {
+    constexpr int HB = kHistTotal / NB;   // shells per pass
     extern __shared__ double smem_d[];
-    Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][kHist]
+    Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][HB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, blockIdx.x, Bk);
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -462,8 +471,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
             frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
             pair.setup(T, x, P.r0);
         }
-        for (int plo = wlo; plo <= whi; plo += kHist) {
-            const int phi = min(whi, plo + kHist - 1);
+        for (int plo = wlo; plo <= whi; plo += HB) {
+            const int phi = min(whi, plo + HB - 1);
             const int wn = phi - plo + 1;
             __syncthreads();
             // transpose of the even split: each shell gathers its fine bins (Remark 1)
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
                         const int64_t m = (int64_t)(plo + i - 1) * S + 1 + t;
                         if (m >= P.Mlo && m <= Mhi) acc += (double)Wk[m - P.Mlo];
                     }
-                    Ws[b * kHist + i] = (Real)(acc * S);
+                    Ws[b * HB + i] = (Real)(acc * S);
                 }
             __syncthreads();
             if (Bk.valid) {
@@ -487,7 +496,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_adj_closed(KParams P, const Rea
                 for (int b = 0; b < NB; ++b) part[b] = AT(0);
                 auto sink = [&](int m, auto area) {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) part[b] = fma((AT)area, (AT)Ws[b * kHist + (m - plo)], part[b]);
+                    for (int b = 0; b < NB; ++b) part[b] = fma((AT)area, (AT)Ws[b * HB + (m - plo)], part[b]);
                 };
                 pair.sweep(plo, phi, sink, P.r0);
 #pragma unroll
@@ -527,9 +536,10 @@ template <class AT, int NB, class Real>
 __global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __restrict__ coef,
                                                         double* __restrict__ f)
 {
+    constexpr int HB = kHistTotal / NB;   // bins per pass
     extern __shared__ double hist[];
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, blockIdx.x, Bk);
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -548,12 +558,12 @@ __global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __
         const AT dA = (AT)P.qdA[k];
         int wlo, whi;
         brick_window(P, Bk, T, wlo, whi);
-        for (int plo = wlo; plo <= whi; plo += kHist) {
-            const int phi = min(whi, plo + kHist - 1);
+        for (int plo = wlo; plo <= whi; plo += HB) {
+            const int phi = min(whi, plo + HB - 1);
             const int wn = phi - plo + 1;
             for (int i = threadIdx.x; i < wn; i += kThreads)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) hist[b * kHist + i] = 0.0;
+                for (int b = 0; b < NB; ++b) hist[b * HB + i] = 0.0;
             __syncthreads();
             if (nz) {
                 int mcur = -(1 << 30);
@@ -566,7 +576,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __
                     if (m != mcur) {
                         if (mcur >= plo && mcur <= phi)
 #pragma unroll
-                            for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (mcur - plo)], p0[b] * (double)acc);
+                            for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * HB + (mcur - plo)], p0[b] * (double)acc);
                         mcur = m;
                         acc = cv;
                     } else {
@@ -575,14 +585,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __
                 }
                 if (mcur >= plo && mcur <= phi)
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * kHist + (mcur - plo)], p0[b] * (double)acc);
+                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * HB + (mcur - plo)], p0[b] * (double)acc);
             }
             __syncthreads();
             const int64_t fo = (plo - P.Mlo);
             for (int i = threadIdx.x; i < wn; i += kThreads)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    double v = hist[b * kHist + i];
+                    double v = hist[b * HB + i];
                     if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + fo + i], v);
                 }
             __syncthreads();
@@ -595,10 +605,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_quad(KParams P, const Real* __
                                                         Real* __restrict__ out, double* __restrict__ z64,
                                                         int direct)
 {
+    constexpr int HB = kHistTotal / NB;   // bins per pass
     extern __shared__ double smem_d[];
     Real* Ws = reinterpret_cast<Real*>(smem_d);
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, blockIdx.x, Bk);
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -612,14 +623,14 @@ __global__ __launch_bounds__(kThreads) void k_adj_quad(KParams P, const Real* __
         const AT dA = (AT)P.qdA[k];
         int wlo, whi;
         brick_window(P, Bk, T, wlo, whi);
-        for (int plo = wlo; plo <= whi; plo += kHist) {
-            const int phi = min(whi, plo + kHist - 1);
+        for (int plo = wlo; plo <= whi; plo += HB) {
+            const int phi = min(whi, plo + HB - 1);
             const int wn = phi - plo + 1;
             __syncthreads();
             const int64_t fo = (plo - P.Mlo);
             for (int i = threadIdx.x; i < wn; i += kThreads)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) Ws[b * kHist + i] = W[((int64_t)b * P.K + k) * P.Mcount + fo + i];
+                for (int b = 0; b < NB; ++b) Ws[b * HB + i] = W[((int64_t)b * P.K + k) * P.Mcount + fo + i];
             __syncthreads();
             if (Bk.valid) {
                 AT part[NB];
@@ -632,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_quad(KParams P, const Real* __
                     if (m < plo || m > phi) continue;
                     AT cv = dA * inv_dist<AT>(r2);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) part[b] = fma(cv, (AT)Ws[b * kHist + (m - plo)], part[b]);
+                    for (int b = 0; b < NB; ++b) part[b] = fma(cv, (AT)Ws[b * HB + (m - plo)], part[b]);
                 }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) acc[b] += (double)part[b];
@@ -660,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_count(KParams P, int quad, unsigne
     if (threadIdx.x < 2) red[threadIdx.x] = 0;
     __syncthreads();
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, blockIdx.x, Bk);
     unsigned long long evals = 0, pairs = 0;
     if (Bk.valid) {
         for (int kk = 0; kk < P.nk; ++kk) {
@@ -704,10 +715,11 @@ __device__ __forceinline__ bool voxel_nonzero(const KParams& P, const Brick& Bk,
 // nonzero voxels per brick
 template <class Real>
 __global__ __launch_bounds__(kThreads) void k_support_count(KParams P, const Real* __restrict__ coef, int B,
+                                                             const int32_t* __restrict__ order,
                                                              int32_t* __restrict__ cnt)
 {
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, order[blockIdx.x], Bk);
     const int c = __syncthreads_count(voxel_nonzero(P, Bk, coef, B));
     if (threadIdx.x == 0) cnt[blockIdx.x] = c;
 }
@@ -736,15 +748,18 @@ __global__ __launch_bounds__(kThreads) void k_support_scan(const int32_t* __rest
     if (threadIdx.x == 0) off[n] = carry;
 }
 
-// the nonzero voxels of each brick at the brick's offset, in thread order
+// the nonzero voxels of each brick at the brick's offset, in thread order; bricks
+// in the order `order` (Morton order of the brick coordinates, so that 256
+// consecutive entries lie in a compact cluster of bricks)
 template <class Real>
 __global__ __launch_bounds__(kThreads) void k_support_write(KParams P, const Real* __restrict__ coef, int B,
+                                                             const int32_t* __restrict__ order,
                                                              const int32_t* __restrict__ off,
                                                              int32_t* __restrict__ list)
 {
     __shared__ int wcount[kThreads / 64];
     Brick Bk;
-    brick_setup(P, Bk);
+    brick_setup(P, order[blockIdx.x], Bk);
     const bool nz = voxel_nonzero(P, Bk, coef, B);
     const unsigned long long m = __ballot(nz);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -828,7 +843,7 @@ namespace {
 template <int SHAPE, class AT, class Real, int IL, bool SPARSE = false>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    size_t sh = (size_t)nb * kHist * sizeof(double);
+    size_t sh = (size_t)kHistTotal * sizeof(double);
     switch (nb) {
     case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
@@ -842,7 +857,7 @@ template <int SHAPE, class AT, class Real, int IL>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
-    size_t sh = (size_t)nb * kHist * sizeof(Real);
+    size_t sh = (size_t)kHistTotal * sizeof(Real);
     switch (nb) {
     case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
@@ -873,7 +888,7 @@ hipError_t adj_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* W,
 template <class AT, class Real>
 hipError_t fwd_quad_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    size_t sh = (size_t)nb * kHist * sizeof(double);
+    size_t sh = (size_t)kHistTotal * sizeof(double);
     switch (nb) {
     case 1: k_fwd_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     case 2: k_fwd_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
@@ -887,7 +902,7 @@ template <class AT, class Real>
 hipError_t adj_quad_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                        hipStream_t s)
 {
-    size_t sh = (size_t)nb * kHist * sizeof(Real);
+    size_t sh = (size_t)kHistTotal * sizeof(Real);
     switch (nb) {
     case 1: k_adj_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     case 2: k_adj_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
@@ -917,9 +932,9 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (sparse) {
         // support of the whole batch: the voxels with a nonzero coefficient in any volume
-        k_support_count<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_cnt);
+        k_support_count<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_order, L.sup_cnt);
         k_support_scan<<<1, kThreads, 0, s>>>(L.sup_cnt, L.nbricks, L.sup_off);
-        k_support_write<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_off, L.sup_list);
+        k_support_write<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_order, L.sup_off, L.sup_list);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     for (int b0 = 0; b0 < B;) {
