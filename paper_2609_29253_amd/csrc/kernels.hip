@@ -536,7 +536,7 @@ template <class AT, int NB, class Real>
 __global__ __launch_bounds__(kThreads) void k_fwd_quad(KParams P, const Real* __restrict__ coef,
                                                         double* __restrict__ f)
 {
-    constexpr int HB = kHistTotal / NB;   // bins per pass
+    constexpr int HB = kHistQuad;   // bins per pass
     extern __shared__ double hist[];
     Brick Bk;
     brick_setup(P, blockIdx.x, Bk);
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_quad(KParams P, const Real* __
                                                         Real* __restrict__ out, double* __restrict__ z64,
                                                         int direct)
 {
-    constexpr int HB = kHistTotal / NB;   // bins per pass
+    constexpr int HB = kHistQuad;   // bins per pass
     extern __shared__ double smem_d[];
     Real* Ws = reinterpret_cast<Real*>(smem_d);
     Brick Bk;
@@ -888,7 +888,7 @@ hipError_t adj_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* W,
 template <class AT, class Real>
 hipError_t fwd_quad_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    size_t sh = (size_t)kHistTotal * sizeof(double);
+    size_t sh = (size_t)nb * kHistQuad * sizeof(double);
     switch (nb) {
     case 1: k_fwd_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     case 2: k_fwd_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, coef, f); break;
@@ -902,7 +902,7 @@ template <class AT, class Real>
 hipError_t adj_quad_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                        hipStream_t s)
 {
-    size_t sh = (size_t)kHistTotal * sizeof(Real);
+    size_t sh = (size_t)nb * kHistQuad * sizeof(Real);
     switch (nb) {
     case 1: k_adj_quad<AT, 1, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     case 2: k_adj_quad<AT, 2, Real><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;

@@ -21,6 +21,8 @@ static_assert(kBrickX * kBrickY * kBrickZ == kThreads, "one voxel per thread");
 static_assert(kBrickX == 8 && kBrickY == 8 && kBrickZ == 4, "four 4 x 4 x 4 wave sub-cubes per brick");
 constexpr int kHistTotal = 4096;   // LDS window entries per work-group, shared by its volumes:
                                    // a pass covers kHistTotal / NB shells (32 KB in FP64)
+constexpr int kHistQuad = 1024;    // quadrature kernels: bins per pass and volume (their windows
+                                   // are narrow and more of them fit a CU with 8 KB each)
 constexpr int kMaxNB = 8;          // volumes per launch
 constexpr int kLutN = 1000;        // nodes per axis of the E~ / F~ tables (lookup-table I_l)
 
