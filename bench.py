@@ -371,6 +371,19 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_full, prob.name),
                 "kernel": dom_name,
                 "flops_per_launch": flops, "launch_ms": round(dom_ms, 3), "area_dtype": area_dtype}
+    # the published peak placed on this device: an FMA-only kernel built like the library's
+    try:
+        from paper_2609_29253_amd import _lib
+        pk = _lib.probe_peak(0)
+        meas = pk["fp64_flops" if area_dtype == "f64" else "fp32_flops"] / 1e12
+        roofline["measured_fma_peak"] = round(meas, 2)
+        roofline["frac_of_measured_fma_peak"] = round(achieved / meas, 4)
+        roofline["device"] = {"compute_units": pk["compute_units"], "clock_ghz": round(pk["clock_ghz"], 3),
+                              "fp64_fma_tflops": round(pk["fp64_flops"] / 1e12, 2),
+                              "fp32_fma_tflops_unpacked": round(pk["fp32_flops"] / 1e12, 2)}
+        log(f"[bench] FMA probe: {roofline['device']}")
+    except Exception as exc:   # a measurement aid only; the line stands without it
+        log(f"[bench] FMA probe unavailable: {exc}")
 
     # ---- oracle on the host cores (bounded sample) and accuracy of the sample
     cpu = None
@@ -391,10 +404,31 @@ def main():
         t_a = time.perf_counter() - t
         a_pairs = float(B) * nv * prob.K
         rate = 1.0 / (t_f / f_pairs + t_a / a_pairs)
+        # the same oracle on one host thread, on a smaller sample
+        O.set_threads(1)
+        t = time.perf_counter()
+        O.forward(prob, ksub=ks[:1], kernel=(h, nf))
+        t_f1 = time.perf_counter() - t
+        vs1 = vs[::32]
+        t = time.perf_counter()
+        O.adjoint(prob, vsub=vs1, kernel=(h, nf))
+        t_a1 = time.perf_counter() - t
+        O.set_threads(threads)
+        rate1 = 1.0 / (t_f1 / (float(B) * prob.N) + t_a1 / (float(B) * len(vs1) * prob.K))
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": rate, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"A on transducers {ks.tolist()} over all {prob.N} voxels ({t_f:.1f}s) and A^T on "
                          f"{nv} evenly spaced voxels over all {prob.K} transducers ({t_a:.1f}s), FP64 surface "
-                         f"method; rate = 1/(t_A/pair + t_AT/pair)"}
+                         f"method; rate = 1/(t_A/pair + t_AT/pair)",
+               "value_1_thread": rate1,
+               "sample_1_thread": f"A on transducer {int(ks[0])} ({t_f1:.1f}s) and A^T on {len(vs1)} voxels "
+                                  f"({t_a1:.1f}s)",
+               "cpu_model": model, "host_cpus": os.cpu_count()}
         from numpy.linalg import norm
 
         def rl2(a, b):

@@ -200,6 +200,15 @@ pat_status pat_check_geometry(const pat_transducer* tr, int32_t K, const pat_gri
  *   8 voxel-transducer pairs per volume */
 pat_status pat_query(const pat_ctx* ctx, int32_t what, double* out);
 
+/* Vector-ALU peak of HIP device `device` as this library's kernels are built
+ * (FP32 not packed): an FMA-only kernel, sixteen independent chains per lane
+ * and no memory access in its loop, over eight work-groups per compute unit,
+ * timed with HIP events.  out[0] FP64 FLOP/s, out[1] FP32 FLOP/s (an FMA counts
+ * 2), out[2] compute units, out[3] peak engine clock in GHz (device
+ * properties).  Synchronous; allocates and frees a few MB of device memory.
+ * Measurement aid for placing the published peaks; PAT_E_DEVICE without a GPU. */
+pat_status pat_probe_peak(int32_t device, double* out);
+
 const char* pat_status_string(int32_t status);
 const char* pat_last_error(const pat_ctx* ctx);
 

@@ -23,8 +23,8 @@ PAT_PHI_CONE, PAT_PHI_WENDLAND2 = 0, 1
 PAT_EIR_GAUSS_COS, PAT_EIR_SAMPLED = 0, 1
 
 EXPORTED = ["pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_adjoint",
-            "pat_build_kernel", "pat_check_geometry", "pat_query", "pat_status_string", "pat_last_error",
-            "pat_destroy"]
+            "pat_build_kernel", "pat_check_geometry", "pat_query", "pat_probe_peak", "pat_status_string",
+            "pat_last_error", "pat_destroy"]
 
 
 class PatError(RuntimeError):
@@ -89,6 +89,7 @@ def lib():
                                    P(c.c_double), c.c_int64, P(c.c_int64), P(c.c_int64)]
     L.pat_check_geometry.argtypes = [P(Transducer), c.c_int32, P(Grid), c.c_double, P(c.c_double)]
     L.pat_query.argtypes = [c.c_void_p, c.c_int32, P(c.c_double)]
+    L.pat_probe_peak.argtypes = [c.c_int32, P(c.c_double)]
     L.pat_status_string.argtypes = [c.c_int32]
     L.pat_status_string.restype = c.c_char_p
     L.pat_last_error.argtypes = [c.c_void_p]
@@ -96,7 +97,7 @@ def lib():
     L.pat_destroy.argtypes = [c.c_void_p]
     L.pat_destroy.restype = None
     for name in ("pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_adjoint",
-                 "pat_build_kernel", "pat_check_geometry", "pat_query"):
+                 "pat_build_kernel", "pat_check_geometry", "pat_query", "pat_probe_peak"):
         getattr(L, name).restype = c.c_int32
     _lib = L
     return L
@@ -133,3 +134,10 @@ def grid_struct(n, origin, spacing):
         g.origin[a] = float(origin[a])
     g.spacing = float(spacing)
     return g
+
+
+def probe_peak(device: int = 0) -> dict:
+    """Measured FP64 / FP32 FMA throughput of the device (pat_probe_peak)."""
+    out = (ctypes.c_double * 4)()
+    check(lib().pat_probe_peak(int(device), out))
+    return {"fp64_flops": out[0], "fp32_flops": out[1], "compute_units": int(out[2]), "clock_ghz": out[3]}
