@@ -519,8 +519,11 @@ static void pair_setup(const double* tr, const double* x, opair* P)
         double R = tr[12], th = tr[13], Lz = tr[14];
         P->R = R;
         P->rho = sqrt(x1 * x1 + x2 * x2);
+        /* focal line (Sec. 4.2): rho at rounding level (below 1e-10 R) is the
+           rho = 0 case, whose angle atan2 would take from rounding noise */
+        if (P->rho <= 1e-10 * R) P->rho = 0.0;
         P->J0 = R;
-        double thi = atan2(x2, x1);
+        double thi = P->rho > 0.0 ? atan2(x2, x1) : 0.0;
         double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
         v1 = -Lz - x3;
         v2 = Lz - x3;
