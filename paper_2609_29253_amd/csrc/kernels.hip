@@ -253,7 +253,11 @@ struct CylinderPair {
     {
         WInt U, V;
         double R = T.p[0], th = T.p[1], Lz = T.p[2];
+        // a voxel on the focal line (rho = 0, Sec. 4.2) has no angular position;
+        // rounding of its frame coordinates leaves rho at ~1e-16 of them, which
+        // is snapped to 0 so that its angle is 0 rather than an arbitrary one
         double rho = sqrt64(x[0] * x[0] + x[1] * x[1]);
+        if (rho <= 1e-10 * R) rho = 0.0;
         double thi = (rho > 0.0) ? atan2(x[1], x[0]) : 0.0;
         P.R = R;
         P.dm = fabs(R - rho);
