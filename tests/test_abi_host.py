@@ -105,3 +105,7 @@ def test_forward_without_geometry_is_a_state_error():
     out = ctypes.c_double(0)
     assert L.pat_query(None, 6, ctypes.byref(out)) == 0 and out.value == _lib.ABI_VERSION
     assert L.pat_forward(None, None, None, 1, None) == 1
+    assert L.pat_forward_sparse(None, None, None, 1, None) == 1
+    assert L.pat_adjoint(None, None, None, 1, None) == 1
+    out4 = (ctypes.c_double * 4)()
+    assert L.pat_probe_peak(0, None) == 1
