@@ -107,5 +107,4 @@ def test_forward_without_geometry_is_a_state_error():
     assert L.pat_forward(None, None, None, 1, None) == 1
     assert L.pat_forward_sparse(None, None, None, 1, None) == 1
     assert L.pat_adjoint(None, None, None, 1, None) == 1
-    out4 = (ctypes.c_double * 4)()
     assert L.pat_probe_peak(0, None) == 1
