@@ -78,7 +78,7 @@ CASES = {
 def test_cylinder_areas_at_degenerate_positions(case):
     tr = _tr()
     x = np.array(CASES[case])
-    fs = 40e6
+    fs = 200e6
     l0, a = O.pair_areas(tr, x, C, 0.0, fs)
     dr = C / fs
     tot = 2 * tr[13] * tr[12] * 2 * tr[14]
