@@ -42,11 +42,17 @@ PEAKS = {"f32": 157.3e12, "f64": 78.6e12}
 
 
 def kernel_source_hash():
+    """Hash of the device sources with comments and blank space removed: a
+    change of the kernels' code changes it, a change of their comments does not."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("area.h", "kernels.hip", "kernels.h", "patop_internal.h"):
-        with open(os.path.join(ROOT, "paper_2609_29253_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2609_29253_amd", "csrc", f)) as fh:
+            txt = fh.read()
+        txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", " ", txt)
+        h.update(" ".join(txt.split()).encode())
     return h.hexdigest()[:16]
 
 

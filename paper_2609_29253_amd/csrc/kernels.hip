@@ -2,6 +2,8 @@
 //
 // Forward A (Alg. 1):
 //   1. k_fill            f <- 0  (FP64 fine-bin coefficients, [B][K][Mcount])
+//   (sparse forward: k_support_count / _scan / _write list the voxels that are
+//    nonzero in some volume, and k_fwd_closed strides groups of 256 of them)
 //   2. k_fwd_closed /    one work-group per (voxel brick, chunk of transducers):
 //      k_fwd_quad        for each transducer, every voxel of the brick adds
 //                        p0 * |M_i^m| (Alg. 3, Eq. ui_area) or p0 * dA / r into the
