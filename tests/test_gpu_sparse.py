@@ -111,6 +111,25 @@ def test_sparse_forward_fine_grid(gpu, mode, step):
     assert e_self < 1e-12 and e_ref < 1e-11
 
 
+def test_sparse_forward_batches_beyond_one_launch(gpu):
+    """Ten volumes: the launches take them in chunks of at most eight, all over
+    the support of the whole batch."""
+    from paper_2609_29253_amd.operator import PatOperator
+    p = P.small_case(P.CYLINDER, n=9, K=3, L=260, B=10, seed=12)
+    coef = p.coef.copy()
+    rng = np.random.default_rng(14)
+    for b in range(coef.shape[0]):
+        coef[b, rng.random(p.N) < 0.7 + 0.02 * b] = 0.0
+    op = PatOperator.from_problem(p, mode="closed", precision="fp64", max_batch=10)
+    c = torch.tensor(coef, device=gpu)
+    s_full = op.forward(c).cpu().numpy()
+    s_sp = op.forward(c, sparse=True).cpu().numpy()
+    op.close()
+    assert rel_l2(s_sp, s_full) < 1e-12
+    for b in (0, 7, 8, 9):
+        assert rel_l2(s_sp[b], O.forward(p, coef=coef[b:b + 1])[0]) < 1e-11
+
+
 def test_sparse_forward_rejects_quadrature(gpu):
     from paper_2609_29253_amd import _lib
     from paper_2609_29253_amd.operator import PatOperator
