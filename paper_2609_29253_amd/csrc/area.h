@@ -100,7 +100,7 @@ __device__ __forceinline__ double sqrt_t(double x) { return x > 0.0 ? x * rsq64(
 __device__ __forceinline__ float atan2_t(float y, float x)
 {
     if (y <= 0.2f * x) {
-        float t = y / x, u = t * t;
+        float t = y * __builtin_amdgcn_rcpf(x), u = t * t;
         float p = fmaf(u, fmaf(u, fmaf(u, fmaf(u, fmaf(u, fmaf(u, 1.0f / 13, -1.0f / 11), 1.0f / 9), -1.0f / 7),
                                        1.0f / 5), -1.0f / 3), 1.0f);
         return t * p;
@@ -111,10 +111,20 @@ __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, 
 __device__ __forceinline__ float atan_t(float x) { return atanf(x); }
 __device__ __forceinline__ double atan_t(double x) { return atan(x); }
 
+// 1/x from the hardware reciprocal: v_rcp_f32 (1 ulp) in FP32, v_rcp_f64 with
+// two Newton steps in FP64
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 template <class T>
 __device__ __forceinline__ T sdiv(T n, T d)
 {
-    return d > T(0) ? n / d : T(0);
+    return d > T(0) ? n * rcp_t(d) : T(0);
 }
 
 // atan(x) - x for x >= 0 without cancellation: halving
@@ -129,7 +139,7 @@ template <> struct AtanMx<float> {
         float acc = 0.0f, scale = 1.0f;
         for (int i = 0; i < 4 && x >= 0.1f; ++i) {
             float q = 1.0f + __builtin_sqrtf(fmaf(x, x, 1.0f));
-            float iq = 1.0f / q;
+            float iq = __builtin_amdgcn_rcpf(q);
             acc = fmaf(-scale * x * x * x, iq * iq, acc);
             x *= iq;
             scale *= 2.0f;
@@ -175,8 +185,8 @@ __device__ __forceinline__ T corr(T p, T s0, T dl, T w0, T w1)
 {
     T ws = w0 + w1;
     if (!(p > T(0)) || !(dl > T(0)) || !(ws > T(0))) return T(0);
-    T dw = dl / ws;
-    T x = p * dw / fma(p, p, w0 * w1);
+    T dw = dl * rcp_t(ws);
+    T x = p * dw * rcp_t(fma(p, p, w0 * w1));
     return fma(s0, AtanMx<T>::eval(x), -x * w0 * dw);
 }
 
