@@ -275,6 +275,53 @@ def run_lib(torch, dev, log):
     return rows
 
 
+def run_cpu_table(torch, dev, log):
+    """Per configuration: the closed form's A + A^T rate on the GPU (FP32 I/O) and
+    the oracle's on the host, on all its threads and on one, each over a bounded
+    sample (A on a few transducers over every voxel, A^T on a few voxels over
+    every transducer), with the GPU / oracle ratio."""
+    import numpy as np
+    import oracle as O
+    from paper_2609_29253_amd.operator import PatOperator
+    rows = {}
+    threads = O.num_threads()
+    for name in ("cfg1", "cfg2", "cfg3", "cfg5"):
+        prob = build_workload(name)
+        B = prob.coef.shape[0]
+        op = PatOperator.from_problem(prob, mode="closed", precision="fp32", max_batch=B)
+        coef = torch.tensor(prob.coef, dtype=torch.float32, device=dev)
+        y = torch.tensor(prob.y, dtype=torch.float32, device=dev)
+        wall, f_ms, a_ms = time_op(op, coef, y, 2, 1, torch)
+        op.close()
+        gpu = float(B) * prob.N * prob.K / ((f_ms + a_ms) * 1e-3)
+        h, nf = O.kernel_of(prob)
+
+        def rates(nk, nv):
+            ks = np.linspace(0, prob.K - 1, nk).astype(np.int32)
+            vs = np.linspace(0, prob.N - 1, nv).astype(np.int64)
+            t = time.perf_counter()
+            O.forward(prob, ksub=ks, kernel=(h, nf))
+            tf = time.perf_counter() - t
+            t = time.perf_counter()
+            O.adjoint(prob, vsub=vs, kernel=(h, nf))
+            ta = time.perf_counter() - t
+            fw, ad = float(B) * prob.N * nk / tf, float(B) * nv * prob.K / ta
+            return {"forward_pairs_per_s": fw, "adjoint_pairs_per_s": ad,
+                    "a_plus_at_pairs_per_s": 1.0 / (1.0 / fw + 1.0 / ad),
+                    "sample": f"A on {nk} transducers over all voxels ({tf:.1f}s), A^T on {nv} voxels ({ta:.1f}s)"}
+
+        small = prob.N * prob.K < 5e7          # cfg1: every transducer, more voxels
+        r_all = rates(prob.K if small else threads, 4096 if small else 1024)
+        O.set_threads(1)
+        r_one = rates(prob.K if small else 1, 1024 if small else 256)
+        O.set_threads(threads)
+        rows[name] = {"workload": prob.name, "gpu_pairs_per_s": gpu, "oracle_threads": threads,
+                      "oracle": r_all, "oracle_1_thread": r_one,
+                      "gpu_over_oracle": gpu / r_all["a_plus_at_pairs_per_s"]}
+        log(f"[bench] cpu table: {rows[name]}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +343,9 @@ def main():
     ap.add_argument("--lib", action="store_true",
                     help="only the LIB-scale rows (sparse forward at U = 61, dense A + A^T at U = 11 on a "
                          "sub-scan), printed as one JSON object instead of the benchmark line")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only the per-configuration GPU and oracle rates (cfg1, cfg2, cfg3, cfg5), printed as one "
+                         "JSON object instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator is built and timed on a single MI355X; "
@@ -309,6 +359,10 @@ def main():
     if args.lib:
         dev = torch.device("cuda", 0)
         print(json.dumps({"lib_rows": run_lib(torch, dev, log)}), flush=True)
+        return
+    if args.cpu_table:
+        dev = torch.device("cuda", 0)
+        print(json.dumps({"cpu_table": run_cpu_table(torch, dev, log)}), flush=True)
         return
 
     t_build = time.perf_counter()
