@@ -150,7 +150,9 @@ pat_status pat_create(pat_ctx** out, int32_t device);
  * Allocates the context's workspace for params->max_batch volumes.
  * Synchronises the device once.  tr[K], grid, kernel and params are read only
  * during the call.  Errors: PAT_E_ARG, PAT_E_FRAME, PAT_E_SHAPE,
- * PAT_E_SEPARATION, PAT_E_KERNEL, PAT_E_DEVICE, PAT_E_OOM; on error the
+ * PAT_E_SEPARATION, PAT_E_KERNEL, PAT_E_DEVICE, PAT_E_OOM, and
+ * PAT_E_UNSUPPORTED beyond the limits: 2^31 voxels or more, U > 65536, a fine
+ * time axis (bins that can reach a sample) reaching beyond +-2^30; on error the
  * previous geometry, if any, is dropped (the context returns to PAT_E_STATE). */
 pat_status pat_set_geometry(pat_ctx* ctx, const pat_transducer* tr, int32_t K,
                             const pat_grid* grid, const pat_kernel* kernel,

@@ -50,6 +50,8 @@ struct pat_ctx {
 
 namespace {
 
+constexpr int32_t kMaxU = 1 << 16;   // up-sampling factors beyond this are rejected
+
 int64_t floordiv64(int64_t a, int64_t b)
 {
     int64_t q = a / b;
@@ -220,6 +222,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!(p.sound_speed > 0.0) || !(p.fs > 0.0) || !(p.t0 >= 0.0) || !std::isfinite(p.t0) || p.L < 1 || p.U < 1 ||
         p.max_batch < 1 || p.flags != 0 || p.reserved != 0)
         return fail(c, PAT_E_ARG, "invalid sampling parameters");
+    if (p.U > kMaxU) return fail(c, PAT_E_UNSUPPORTED, "U above 65536");
     if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE && p.area_mode != PAT_AREA_TRAPEZOID &&
         p.area_mode != PAT_AREA_LUT)
         return fail(c, PAT_E_ARG, "invalid area_mode");
@@ -241,8 +244,10 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
                  dlow);
         return fail(c, st, buf);
     }
+    // each extent is >= 1 here; the product is formed only once it is known to fit
+    if ((double)grid->n[0] * (double)grid->n[1] * (double)grid->n[2] >= 2147483648.0)
+        return fail(c, PAT_E_UNSUPPORTED, "2^31 voxels or more");
     const int64_t N = grid->n[0] * grid->n[1] * grid->n[2];
-    if (N >= (int64_t)1 << 31) return fail(c, PAT_E_UNSUPPORTED, "more than 2^31 voxels");
 
     const double dr = p.sound_speed / (p.U * p.fs);
     const double r0 = p.t0 * p.U * p.fs;

@@ -67,3 +67,28 @@ def test_degenerate_geometry(gpu, case, mode, prec):
     assert np.all(np.isfinite(s)) and np.all(np.isfinite(z))
     assert np.linalg.norm(s_ref) > 0
     assert es < TOL[prec] and ez < TOL[prec]
+
+
+def test_size_limits_are_rejected(gpu):
+    """Sizes beyond the library's limits fail with PAT_E_UNSUPPORTED, before
+    any product of them can overflow: 2^31 voxels or more (also with extents
+    whose product exceeds 2^63) and U above 65536.  The grid keeps its spacing
+    small enough to stay clear of the transducers."""
+    from paper_2609_29253_amd import _lib
+    from paper_2609_29253_amd.operator import PatOperator, build_kernel
+    p = P.small_case(P.PLANAR, n=5, K=2, U=1, B=1, L=64)
+    h, nf = build_kernel(p.phi_type, p.kappa, p.eir, p.sound_speed, p.fs, p.U)
+    args = (p.tr.packed, p.grid.origin, h, nf, p.kappa, p.sound_speed, p.fs, p.t0, p.L)
+
+    def make(n, spacing, U=1):
+        packed, origin, hh, nff, kappa, c, fs, t0, L_ = args
+        return PatOperator(packed, n, origin, spacing, hh, nff, kappa, c, fs, t0, L_, U)
+
+    for n in [(2048, 1024, 1024), (1 << 40, 1 << 40, 1 << 40)]:
+        with pytest.raises(_lib.PatError) as e:
+            make(n, 1e-15)
+        assert e.value.status == 9, n
+    with pytest.raises(_lib.PatError) as e:
+        make(p.grid.n, p.grid.spacing, U=70000)
+    assert e.value.status == 9
+    make(p.grid.n, p.grid.spacing).close()      # the same system within the limits is accepted
