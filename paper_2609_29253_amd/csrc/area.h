@@ -454,6 +454,10 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // ~eps^8 / 4 for eps = max |1 - x_i / A|, so the duplication stops once
 // eps < 1/35 (relative error ~1e-13).  TABLE: stop at eps < 1e-4 instead
 // (truncation far below rounding) and also return F = s R_F(c^2, D^2, 1).
+// The duplication runs on 4^n times the n-th iterates: a step then adds
+// lambda to each (no scaling), the stopping test compares 4^n A_n with the
+// fixed initial deviation, and the factors 2^n that the scaling leaves on
+// R_F and on the R_D series are applied once at the end.
 template <int NW, bool TABLE = false>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu, double* f_out = nullptr)
 {
@@ -463,22 +467,22 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double AD = (x + y + 3.0 * z) * 0.2;
     double dev = fmax(fabs(AF - x), fmax(fabs(AF - y), fabs(AF - z)));
     dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
-    const double Qf = TABLE ? 1.0e4 : 35.0;
+    const double thr = (TABLE ? 1.0e4 : 35.0) * dev;
     const int itmax = TABLE ? 40 : 12;
-    double p4 = 1.0, sumD = 0.0;
+    double p2 = 1.0, sumD = 0.0;
 #pragma unroll 1
-    for (int it = 0; it < itmax && p4 * Qf * dev >= fmin(AF, AD); ++it) {
+    for (int it = 0; it < itmax && thr >= fmin(AF, AD); ++it) {
         double lam = fma(sx, sy, fma(sx, sz, sy * sz));
-        sumD = fma(p4, rcp64(sz * (z + lam)), sumD);
-        x = 0.25 * (x + lam);
-        y = 0.25 * (y + lam);
-        z = 0.25 * (z + lam);
-        AF = 0.25 * (AF + lam);
-        AD = 0.25 * (AD + lam);
-        p4 *= 0.25;
+        sumD = fma(p2, rcp64(sz * (z + lam)), sumD);
+        x += lam;
+        y += lam;
+        z += lam;
+        AF += lam;
+        AD += lam;
+        p2 *= 2.0;
         sx = sqrt64<NW>(x);
         sy = sqrt64<NW>(y);
-        sz = sqrt64<NW>(z);
+        sz = z * rsq64<NW>(z);
     }
     double rAF = rsq64<NW>(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
@@ -486,7 +490,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double E22 = E2 * E2;
     double sf = 1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E22 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0) -
                 E22 * E2 * (5.0 / 208.0) + E3 * E3 * (3.0 / 104.0) + E22 * E3 * (1.0 / 16.0);
-    double rf = sf * rAF;
+    double rf = sf * rAF * p2;
     double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
     Y = (AD - y) * iAD;
@@ -497,7 +501,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D22 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
                  D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0) - D22 * D2 * (1.0 / 16.0) + D3 * D3 * (3.0 / 40.0) +
                  D2 * D4 * (3.0 / 20.0) + D22 * D3 * (45.0 / 272.0) - (D3 * D4 + D2 * D5) * (9.0 / 68.0);
-    double rd = fma(p4 * ser * iAD, rAD, 3.0 * sumD);
+    double rd = fma(p2 * ser * iAD, rAD, 3.0 * sumD);
     if (TABLE) *f_out = s * rf;
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
 }
@@ -589,42 +593,6 @@ __device__ __forceinline__ double asin_small(double u)
     return fma(u * y, p, u);
 }
 
-// Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I
-// (Eq. cyl_Il; the chord of the level curve, Eq. trapezoid_Il, or the tables)
-template <int NW, int IL = kIlExact>
-__device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
-{
-    double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
-    if (!(K > 0.0)) {
-        E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
-        return;
-    }
-    double isK = rsq64<NW>(K);
-    cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
-    cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
-    double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
-    if (!(cr > 0.0)) { E.I = 0.0; return; }
-    if (IL == kIlTrapezoid) {
-        // (beta - alpha)/2 (Psi(alpha) + Psi(beta)) with Psi = sqrt(K) Delta
-        const double cs = fma(E.cb, E.ca, E.sb * E.sa);   // cos(beta/2 - alpha/2)
-        const double sg = (cr <= 0.05 && cs > 0.0) ? asin_small(cr) : atan2(cr, cs);
-        E.I = K * isK * sg * (E.da + E.db);
-        return;
-    }
-    double nu = P.mu * isK * isK;
-    if (IL == kIlTable) {
-        E.I = 2.0 * K * isK * lut_de<NW>(P.lut, E.sa, E.sb, nu);
-        return;
-    }
-    double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
-    double idn = rcp64(den);
-    double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
-    double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
-    double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
-    double es = ellip_e_scd<NW>(ss, cs, ds, nu);
-    E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
-}
-
 // 2 atan(x) for 0 <= x <= 0.2: odd Taylor series through x^23
 __device__ __forceinline__ double twice_atan_small(double x)
 {
@@ -643,6 +611,63 @@ __device__ __forceinline__ double twice_atan_small(double x)
     return 2.0 * fma(-x * y, p, x);
 }
 
+// atan(t) for 0 <= t <= 1: two halvings of the angle, tan(x/2) = t / (1 +
+// sqrt(1 + t^2)), take t below tan(pi/16) < 0.2, where the series above holds
+__device__ __forceinline__ double atan_unit(double t)
+{
+    t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
+    t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
+    return 2.0 * twice_atan_small(t);
+}
+
+// atan2(y, x) on the full circle from atan_unit of min/max(|x|, |y|), with
+// the octant restored by reflections; 0 for x = y = 0
+__device__ __forceinline__ double atan2_full(double y, double x)
+{
+    const double ax = fabs(x), ay = fabs(y);
+    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    double a = mx > 0.0 ? atan_unit(mn * rcp64_full(mx)) : 0.0;
+    if (ay > ax) a = 0.5 * M_PI - a;
+    if (x < 0.0) a = M_PI - a;
+    return copysign(a, y);
+}
+
+// Alg. 4 triple at the edge of radius r: half-angle state of alpha, beta and I
+// (Eq. cyl_Il; the chord of the level curve, Eq. trapezoid_Il, or the tables)
+template <int NW, int IL = kIlExact>
+__device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
+{
+    double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
+    if (!(K > 0.0)) {
+        E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
+        return;
+    }
+    double isK = rsq64<NW>(K);
+    cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
+    cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
+    double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
+    if (!(cr > 0.0)) { E.I = 0.0; return; }
+    if (IL == kIlTrapezoid) {
+        // (beta - alpha)/2 (Psi(alpha) + Psi(beta)) with Psi = sqrt(K) Delta
+        const double cs = fma(E.cb, E.ca, E.sb * E.sa);   // cos(beta/2 - alpha/2)
+        const double sg = (cr <= 0.05 && cs > 0.0) ? asin_small(cr) : atan2_full(cr, cs);
+        E.I = K * isK * sg * (E.da + E.db);
+        return;
+    }
+    double nu = P.mu * isK * isK;
+    if (IL == kIlTable) {
+        E.I = 2.0 * K * isK * lut_de<NW>(P.lut, E.sa, E.sb, nu);
+        return;
+    }
+    double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
+    double idn = rcp64(den);
+    double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
+    double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
+    double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
+    double es = ellip_e_scd<NW>(ss, cs, ds, nu);
+    E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
+}
+
 // The steps of both end-point angles between consecutive edges, from the sine
 // cr and cosine dt of the half-angle step (negative steps count as zero).  When
 // every active lane of the wave has a small step with dt > 0 the step is
@@ -658,8 +683,8 @@ __device__ __forceinline__ void twice_angles(double cra, double dta, double crb,
     }
     const double xa = cra > 0.0 ? cra * rcp64(dta) : 0.0;
     const double xb = crb > 0.0 ? crb * rcp64(dtb) : 0.0;
-    da = (xa > 0.2 || !(dta > 0.0)) ? (cra > 0.0 ? 2.0 * atan2(cra, dta) : 0.0) : twice_atan_small(xa);
-    db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2(crb, dtb) : 0.0) : twice_atan_small(xb);
+    da = (xa > 0.2 || !(dta > 0.0)) ? (cra > 0.0 ? 2.0 * atan2_full(cra, dta) : 0.0) : twice_atan_small(xa);
+    db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2_full(crb, dtb) : 0.0) : twice_atan_small(xb);
 }
 
 template <int NW, int IL, class Sink>

@@ -260,7 +260,7 @@ struct CylinderPair {
         // is snapped to 0 so that its angle is 0 rather than an arbitrary one
         double rho = sqrt64(x[0] * x[0] + x[1] * x[1]);
         if (rho <= 1e-10 * R) rho = 0.0;
-        double thi = (rho > 0.0) ? atan2(x[1], x[0]) : 0.0;
+        double thi = (rho > 0.0) ? atan2_full(x[1], x[0]) : 0.0;
         P.R = R;
         P.dm = fabs(R - rho);
         P.mu = 4.0 * R * rho;
