@@ -26,14 +26,14 @@ METRIC = "A+Aᵀ voxel×transducer pairs/s, closed-form FP32 vs quadrature/FP64 
 # Algorithmic FLOPs per area evaluation (one quadrant of one voxel-transducer
 # pair in one fine bin), with the per-pair and per-quadrant setup spread over
 # the evaluations: the operations of the device formulas counted one by one
-# (FMA = 2, add/mul = 1, sqrt/rsq/rcp = 1, library sin/cos/atan at their
-# polynomial length) over a sample of the 128^3 x 256-cylinder workload, where
-# the Carlson loop runs its actual number of steps.
+# (FMA = 2, add/mul = 1, sqrt/rsq/rcp = 1; the cylinder path calls no library
+# routine) over a sample of the 128^3 x 256-cylinder workload, where the
+# Carlson loop runs its actual number of steps.
 FLOPS_PER_EVAL = {
     ("closed", 0, "fp32"): 106.0,   # planar, FP32 cancellation-free form (static count of the common path)
     ("closed", 0, "fp64"): 106.0,
-    ("closed", 1, "fp32"): 327.5,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
-    ("closed", 1, "fp64"): 382.3,   # cylinder, two Newton steps
+    ("closed", 1, "fp32"): 309.7,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
+    ("closed", 1, "fp64"): 364.5,   # cylinder, two Newton steps
 }
 # per surface point of the quadrature (FP64 distance + bin test, FP32/FP64 weight)
 FLOPS_PER_POINT = 14.0
@@ -336,6 +336,9 @@ def main():
                     help="one forward and one adjoint of the closed FP32 variant, nothing else")
     ap.add_argument("--profile-mode", default="closed", choices=["closed", "quadrature", "trapezoid", "lut"],
                     help="area method of --profile-only")
+    ap.add_argument("--probe", action="store_true",
+                    help="with --profile-only: also run the FMA probe (its kernels' counters give the clock "
+                         "under a pure FMA load for comparison)")
     ap.add_argument("--next", action="store_true",
                     help="also time the approximate variants (trapezoidal and lookup-table cylinder I_l and "
                          "refined quadratures on the workload; the coarse area grid on the 128^3 cylinder "
@@ -411,6 +414,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] profile run done: one A and one A^T of {prob.name} ({args.profile_mode})")
         op.close()
+        if args.probe:
+            from paper_2609_29253_amd import _lib
+            log(f"[bench] FMA probe: {_lib.probe_peak(0)}")
         return
     main_res = run_variant("closed", "fp32", args.steps, args.warmup)
     results["closed_fp32"] = main_res

@@ -82,13 +82,29 @@ __device__ __forceinline__ double rsq64(double x)
     return r;
 }
 
+// sqrt of x > 0 from y = v_rsq_f64(x) (relative error ~2^-24): g = x y is
+// corrected by the residual x - g^2 times h = y/2 (one step: ~2^-48); two
+// steps first refine g and h together (Goldschmidt), then take the residual
+// step (full precision)
+template <int NEWTON = 2>
+__device__ __forceinline__ double sqrt64_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    if (NEWTON >= 2) {
+        const double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+    }
+    return fma(fma(-g, g, x), h, g);
+}
+
 // sqrt(max(x, 1e-300)): branch free; returns 1e-150 instead of 0 for x <= 0,
 // which is below any length or cosine that enters a sum here
 template <int NEWTON = 2>
 __device__ __forceinline__ double sqrt64(double x)
 {
-    x = fmax(x, 1e-300);
-    return x * rsq64<NEWTON>(x);
+    return sqrt64_pos<NEWTON>(fmax(x, 1e-300));
 }
 
 __device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
@@ -457,11 +473,14 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // The duplication runs on 4^n times the n-th iterates: a step then adds
 // lambda to each (no scaling), the stopping test compares 4^n A_n with the
 // fixed initial deviation, and the factors 2^n that the scaling leaves on
-// R_F and on the R_D series are applied once at the end.
+// R_F and on the R_D series are applied once at the end.  With c^2, D^2 <= 1
+// = z, z stays the largest argument, so A_D = (x + y + 3z)/5 >= A_F = (x + y
+// + z)/3 and the test needs A_F only.  x and y start at >= 1e-300, so every
+// square root in the loop has a positive argument.
 template <int NW, bool TABLE = false>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu, double* f_out = nullptr)
 {
-    double x = c * c, y = dl * dl, z = 1.0;
+    double x = fmax(c * c, 1e-300), y = fmax(dl * dl, 1e-300), z = 1.0;
     double sx = fabs(c), sy = dl, sz = 1.0;
     double AF = (x + y + z) * (1.0 / 3.0);
     double AD = (x + y + 3.0 * z) * 0.2;
@@ -471,25 +490,25 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     const int itmax = TABLE ? 40 : 12;
     double p2 = 1.0, sumD = 0.0;
 #pragma unroll 1
-    for (int it = 0; it < itmax && thr >= fmin(AF, AD); ++it) {
+    for (int it = 0; it < itmax && thr >= AF; ++it) {
         double lam = fma(sx, sy, fma(sx, sz, sy * sz));
         sumD = fma(p2, rcp64(sz * (z + lam)), sumD);
         x += lam;
         y += lam;
         z += lam;
         AF += lam;
-        AD += lam;
         p2 *= 2.0;
-        sx = sqrt64<NW>(x);
-        sy = sqrt64<NW>(y);
-        sz = z * rsq64<NW>(z);
+        sx = sqrt64_pos<NW>(x);
+        sy = sqrt64_pos<NW>(y);
+        sz = sqrt64_pos<NW>(z);
     }
+    AD = (x + y + 3.0 * z) * 0.2;
     double rAF = rsq64<NW>(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
-    double E22 = E2 * E2;
-    double sf = 1.0 - E2 * 0.1 + E3 * (1.0 / 14.0) + E22 * (1.0 / 24.0) - E2 * E3 * (3.0 / 44.0) -
-                E22 * E2 * (5.0 / 208.0) + E3 * E3 * (3.0 / 104.0) + E22 * E3 * (1.0 / 16.0);
+    // 1 - E2/10 + E3/14 + E2^2/24 - 3 E2 E3/44 - 5 E2^3/208 + 3 E3^2/104 + E2^2 E3/16
+    double sf = fma(E2, fma(E2, fma(E2, -5.0 / 208.0, 1.0 / 24.0), -0.1), 1.0);
+    sf = fma(E3, fma(E2, fma(E2, 1.0 / 16.0, -3.0 / 44.0), fma(E3, 3.0 / 104.0, 1.0 / 14.0)), sf);
     double rf = sf * rAF * p2;
     double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
@@ -497,10 +516,12 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     Z = -(X + Y) * (1.0 / 3.0);
     double XY = X * Y, Z2 = Z * Z;
     double D2 = XY - 6.0 * Z2, D3 = (3.0 * XY - 8.0 * Z2) * Z, D4 = 3.0 * (XY - Z2) * Z2, D5 = XY * Z2 * Z;
-    double D22 = D2 * D2;
-    double ser = 1.0 - D2 * (3.0 / 14.0) + D3 * (1.0 / 6.0) + D22 * (9.0 / 88.0) - D4 * (3.0 / 22.0) -
-                 D2 * D3 * (9.0 / 52.0) + D5 * (3.0 / 26.0) - D22 * D2 * (1.0 / 16.0) + D3 * D3 * (3.0 / 40.0) +
-                 D2 * D4 * (3.0 / 20.0) + D22 * D3 * (45.0 / 272.0) - (D3 * D4 + D2 * D5) * (9.0 / 68.0);
+    // 1 - 3 D2/14 + D3/6 + 9 D2^2/88 - 3 D4/22 - 9 D2 D3/52 + 3 D5/26 - D2^3/16 + 3 D3^2/40
+    //   + 3 D2 D4/20 + 45 D2^2 D3/272 - 9 (D3 D4 + D2 D5)/68, grouped by powers of D2 and D3
+    double t2 = fma(D3, 45.0 / 272.0, fma(D2, -1.0 / 16.0, 9.0 / 88.0));
+    t2 = fma(D2, t2, fma(D3, -9.0 / 52.0, fma(D4, 3.0 / 20.0, fma(D5, -9.0 / 68.0, -3.0 / 14.0))));
+    double t3 = fma(D3, 3.0 / 40.0, fma(D4, -9.0 / 68.0, 1.0 / 6.0));
+    double ser = fma(D2, t2, fma(D3, t3, fma(D4, -3.0 / 22.0, fma(D5, 3.0 / 26.0, 1.0))));
     double rd = fma(p2 * ser * iAD, rAD, 3.0 * sumD);
     if (TABLE) *f_out = s * rf;
     return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
@@ -593,31 +614,19 @@ __device__ __forceinline__ double asin_small(double u)
     return fma(u * y, p, u);
 }
 
-// 2 atan(x) for 0 <= x <= 0.2: odd Taylor series through x^23
-__device__ __forceinline__ double twice_atan_small(double x)
-{
-    double y = x * x;
-    double p = 1.0 / 23;
-    p = fma(y, p, -1.0 / 21);
-    p = fma(y, p, 1.0 / 19);
-    p = fma(y, p, -1.0 / 17);
-    p = fma(y, p, 1.0 / 15);
-    p = fma(y, p, -1.0 / 13);
-    p = fma(y, p, 1.0 / 11);
-    p = fma(y, p, -1.0 / 9);
-    p = fma(y, p, 1.0 / 7);
-    p = fma(y, p, -1.0 / 5);
-    p = fma(y, p, 1.0 / 3);
-    return 2.0 * fma(-x * y, p, x);
-}
-
-// atan(t) for 0 <= t <= 1: two halvings of the angle, tan(x/2) = t / (1 +
-// sqrt(1 + t^2)), take t below tan(pi/16) < 0.2, where the series above holds
+// atan(t) for 0 <= t <= 1: four halvings of the angle, tan(x/2) = t / (1 +
+// sqrt(1 + t^2)), take t below tan(pi/64) < 0.05, where the odd Taylor series
+// through t^13 has its first omitted term below 3e-20 relative.  Its
+// coefficients 1/3 .. 1/13 are taken over the common denominator 45045, so
+// each is an integer that the instruction encodes as a literal.
 __device__ __forceinline__ double atan_unit(double t)
 {
-    t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
-    t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
-    return 2.0 * twice_atan_small(t);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
+    const double y = t * t, y2 = y * y, y3 = y2 * y;
+    const double p = 45045.0 - 15015.0 * y + 9009.0 * y2 - 6435.0 * y3 + 5005.0 * (y2 * y2) -
+                     4095.0 * (y2 * y3) + 3465.0 * (y3 * y3);
+    return (16.0 / 45045.0) * t * p;
 }
 
 // atan2(y, x) on the full circle from atan_unit of min/max(|x|, |y|), with
@@ -671,7 +680,7 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
 // The steps of both end-point angles between consecutive edges, from the sine
 // cr and cosine dt of the half-angle step (negative steps count as zero).  When
 // every active lane of the wave has a small step with dt > 0 the step is
-// 2 asin(cr), with no division; otherwise 2 atan(cr / dt).
+// 2 asin(cr), with no division; otherwise 2 atan2(cr, dt).
 __device__ __forceinline__ void twice_angles(double cra, double dta, double crb, double dtb, double& da,
                                              double& db)
 {
@@ -681,10 +690,8 @@ __device__ __forceinline__ void twice_angles(double cra, double dta, double crb,
         db = 2.0 * asin_small(ub);
         return;
     }
-    const double xa = cra > 0.0 ? cra * rcp64(dta) : 0.0;
-    const double xb = crb > 0.0 ? crb * rcp64(dtb) : 0.0;
-    da = (xa > 0.2 || !(dta > 0.0)) ? (cra > 0.0 ? 2.0 * atan2_full(cra, dta) : 0.0) : twice_atan_small(xa);
-    db = (xb > 0.2 || !(dtb > 0.0)) ? (crb > 0.0 ? 2.0 * atan2_full(crb, dtb) : 0.0) : twice_atan_small(xb);
+    da = cra > 0.0 ? 2.0 * atan2_full(cra, dta) : 0.0;
+    db = crb > 0.0 ? 2.0 * atan2_full(crb, dtb) : 0.0;
 }
 
 template <int NW, int IL, class Sink>

@@ -349,7 +349,7 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
                                           const Real* __restrict__ coef, double* __restrict__ f, double* hist,
                                           double* box)
 {
-    constexpr int HB = kHistTotal / NB;   // shells per pass
+    constexpr int HB = hist_total<SHAPE>() / NB;   // shells per pass
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -414,19 +414,25 @@ constexpr int kSparseGrid = 4096;
 // Dense: work-group (brick, chunk of transducers).  SPARSE: the work items
 // (group of 256 support entries, chunk of P.kchunk transducers) are strided over
 // a fixed grid, since the number of groups is known on the device only.
-// waves per SIMD the closed-form kernels are built for: three, whose 168 VGPRs
-// hold the FP64 cylinder sweep with few spills.  The planar sweep in FP64 for
-// four or eight volumes spills 300 bytes per lane at three and runs faster at
-// two (1.75x for the adjoint of eight volumes); for one volume three is faster
-// despite its spills (9 %).
-template <int SHAPE, class AT, int NB>
-constexpr int closed_waves() { return SHAPE == 0 && sizeof(AT) == 8 && NB >= 4 ? 2 : 3; }
+// waves per SIMD the closed-form kernels are built for.  Cylinders for one or
+// two volumes: four, in 128 VGPRs with a few spills outside the sweep, and a
+// 16 KB histogram so that four work-groups share a CU (2 % faster than three
+// on the 128^3 x 256-cylinder workload); with more volumes, and in the sparse
+// forward, the spills grow (120-210 bytes per lane) and they keep three.  The
+// planar sweep in FP64 for four or eight volumes spills 300 bytes per lane at
+// three and runs faster at two (1.75x for the adjoint of eight volumes); for
+// one volume three is faster despite its spills (9 %).
+template <int SHAPE, class AT, int NB, bool SPARSE = false>
+constexpr int closed_waves()
+{
+    return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 && NB >= 4 ? 2 : 3);
+}
 
 template <int SHAPE, class AT, int NB, class Real, int IL, bool SPARSE>
-__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
+__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
-    extern __shared__ double hist[];   // [NB][kHistTotal / NB]
+    extern __shared__ double hist[];   // [NB][hist_total<SHAPE>() / NB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     if (!SPARSE) {
         Brick Bk;
@@ -455,7 +461,7 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_a
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
 {
-    constexpr int HB = kHistTotal / NB;   // shells per pass
+    constexpr int HB = hist_total<SHAPE>() / NB;   // shells per pass
     extern __shared__ double smem_d[];
     Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][HB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
@@ -849,7 +855,7 @@ namespace {
 template <int SHAPE, class AT, class Real, int IL, bool SPARSE = false>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    size_t sh = (size_t)kHistTotal * sizeof(double);
+    size_t sh = (size_t)hist_total<SHAPE>() * sizeof(double);
     switch (nb) {
     case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
     case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
@@ -863,7 +869,7 @@ template <int SHAPE, class AT, class Real, int IL>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
-    size_t sh = (size_t)kHistTotal * sizeof(Real);
+    size_t sh = (size_t)hist_total<SHAPE>() * sizeof(Real);
     switch (nb) {
     case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
     case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
