@@ -484,8 +484,8 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double sx = fabs(c), sy = dl, sz = 1.0;
     double AF = (x + y + z) * (1.0 / 3.0);
     double AD = (x + y + 3.0 * z) * 0.2;
-    double dev = fmax(fabs(AF - x), fmax(fabs(AF - y), fabs(AF - z)));
-    dev = fmax(dev, fmax(fabs(AD - x), fmax(fabs(AD - y), fabs(AD - z))));
+    // largest |A - x_i| over both means: z is the largest argument and A_D >= A_F
+    const double dev = fmax(z - AF, AD - fmin(x, y));
     const double thr = (TABLE ? 1.0e4 : 35.0) * dev;
     const int itmax = TABLE ? 40 : 12;
     double p2 = 1.0, sumD = 0.0;
@@ -668,13 +668,14 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
         E.I = 2.0 * K * isK * lut_de<NW>(P.lut, E.sa, E.sb, nu);
         return;
     }
-    double den = fma(E.cb, E.cb, E.sb * E.sb * E.da * E.da);   // 1 - nu sin^2 sin^2
+    const double sbda = E.sb * E.da, sbsa = E.sb * E.sa, dd = E.db * E.da, nss = nu * sbsa;
+    double den = fma(E.cb, E.cb, sbda * sbda);   // 1 - nu sin^2 sin^2
     double idn = rcp64(den);
-    double ss = fma(E.sb * E.ca, E.da, -E.sa * E.cb * E.db) * idn;
-    double cs = fma(E.cb, E.ca, E.sb * E.sa * E.db * E.da) * idn;
-    double ds = fma(E.db, E.da, nu * E.sb * E.cb * E.sa * E.ca) * idn;
+    double ss = fma(sbda, E.ca, -E.sa * (E.cb * E.db)) * idn;
+    double cs = fma(E.cb, E.ca, sbsa * dd) * idn;
+    double ds = fma(nss, E.cb * E.ca, dd) * idn;
     double es = ellip_e_scd<NW>(ss, cs, ds, nu);
-    E.I = 2.0 * K * isK * fma(-nu * E.sb * E.sa, ss, es);
+    E.I = 2.0 * K * isK * fma(-nss, ss, es);
 }
 
 // The steps of both end-point angles between consecutive edges, from the sine

@@ -344,12 +344,12 @@ template <class AT, class Real, int IL> struct PairOf<1, AT, Real, IL> {
 // ---------------------------------------------------------------------------
 
 // one brick (or group of support voxels) against transducers kperm[kbeg .. kend)
-template <int SHAPE, class AT, int NB, class Real, int IL>
+template <int SHAPE, class AT, int NB, class Real, int IL, int HT>
 __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int kbeg, int kend,
                                           const Real* __restrict__ coef, double* __restrict__ f, double* hist,
                                           double* box)
 {
-    constexpr int HB = hist_total<SHAPE>() / NB;   // shells per pass
+    constexpr int HB = HT / NB;   // shells per pass
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -428,17 +428,25 @@ constexpr int closed_waves()
     return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 && NB >= 4 ? 2 : 3);
 }
 
+// LDS histogram entries per work-group: 16 KB in FP64 at four waves (four
+// work-groups per CU with the 16 KB interval table), 32 KB otherwise
+template <int SHAPE, class AT, int NB, bool SPARSE = false>
+constexpr int closed_hist()
+{
+    return closed_waves<SHAPE, AT, NB, SPARSE>() == 4 ? kHistCyl : kHistTotal;
+}
+
 template <int SHAPE, class AT, int NB, class Real, int IL, bool SPARSE>
 __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
                                                           double* __restrict__ f)
 {
-    extern __shared__ double hist[];   // [NB][hist_total<SHAPE>() / NB]
+    extern __shared__ double hist[];   // [NB][closed_hist<SHAPE, AT, NB, SPARSE>() / NB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
     if (!SPARSE) {
         Brick Bk;
         brick_setup(P, blockIdx.x, Bk);
         const int kbeg = blockIdx.y * P.kchunk;
-        fwd_brick<SHAPE, AT, NB, Real, IL>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+        fwd_brick<SHAPE, AT, NB, Real, IL, closed_hist<SHAPE, AT, NB, SPARSE>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
         return;
     }
     const int64_t total = *P.sup_total;
@@ -448,7 +456,7 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) 
         Brick Bk;
         brick_setup_sparse(P, it / nchunks, total, Bk);
         const int kbeg = (int)(it % nchunks) * P.kchunk;
-        fwd_brick<SHAPE, AT, NB, Real, IL>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+        fwd_brick<SHAPE, AT, NB, Real, IL, closed_hist<SHAPE, AT, NB, SPARSE>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
     }
 }
 
@@ -461,7 +469,7 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_a
                                                           Real* __restrict__ out, double* __restrict__ z64,
                                                           int direct)
 {
-    constexpr int HB = hist_total<SHAPE>() / NB;   // shells per pass
+    constexpr int HB = closed_hist<SHAPE, AT, NB>() / NB;   // shells per pass
     extern __shared__ double smem_d[];
     Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][HB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
@@ -855,12 +863,12 @@ namespace {
 template <int SHAPE, class AT, class Real, int IL, bool SPARSE = false>
 hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    size_t sh = (size_t)hist_total<SHAPE>() * sizeof(double);
+    constexpr size_t d = sizeof(double);
     switch (nb) {
-    case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    case 4: k_fwd_closed<SHAPE, AT, 4, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
-    default: k_fwd_closed<SHAPE, AT, 8, Real, IL, SPARSE><<<grid, kThreads, sh, s>>>(P, coef, f); break;
+    case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 1, SPARSE>() * d, s>>>(P, coef, f); break;
+    case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 2, SPARSE>() * d, s>>>(P, coef, f); break;
+    case 4: k_fwd_closed<SHAPE, AT, 4, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 4, SPARSE>() * d, s>>>(P, coef, f); break;
+    default: k_fwd_closed<SHAPE, AT, 8, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 8, SPARSE>() * d, s>>>(P, coef, f); break;
     }
     return hipGetLastError();
 }
@@ -869,12 +877,12 @@ template <int SHAPE, class AT, class Real, int IL>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
-    size_t sh = (size_t)hist_total<SHAPE>() * sizeof(Real);
+    constexpr size_t d = sizeof(Real);
     switch (nb) {
-    case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    case 4: k_adj_closed<SHAPE, AT, 4, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
-    default: k_adj_closed<SHAPE, AT, 8, Real, IL><<<grid, kThreads, sh, s>>>(P, W, out, z64, direct); break;
+    case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 1>() * d, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 2>() * d, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_closed<SHAPE, AT, 4, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 4>() * d, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_closed<SHAPE, AT, 8, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 8>() * d, s>>>(P, W, out, z64, direct); break;
     }
     return hipGetLastError();
 }
