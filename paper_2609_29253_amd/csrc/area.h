@@ -459,8 +459,8 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
         dl = sqrt64<NW>((r - q.Db0) * (r + q.Db0)) * isK;
         return;
     }
-    s = sqrt64<NW>(qa + q.musa2) * P.isq_mu;
-    c = sqrt64<NW>(q.mucb2 - qb) * P.isq_mu;
+    s = sqrt64_pos<NW>(qa + q.musa2) * P.isq_mu;   // both arguments > 0 here
+    c = sqrt64_pos<NW>(q.mucb2 - qb) * P.isq_mu;
     dl = v * isK;
 }
 
@@ -646,16 +646,15 @@ __device__ __forceinline__ double atan2_full(double y, double x)
 template <int NW, int IL = kIlExact>
 __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double r, CyEdge& E)
 {
-    double K = (r - P.dm) * (r + P.dm);   // r^2 - (R - rho)^2 = 2 R rho + b(r)
-    if (!(K > 0.0)) {
-        E.sa = E.sb = q.sa; E.ca = E.cb = q.ca; E.da = E.db = 1.0; E.I = 0.0;
-        return;
-    }
-    double isK = rsq64<NW>(K);
+    // K = r^2 - (R - rho)^2 = 2 R rho + b(r).  K <= 0: the shell misses the
+    // surface, r^2 - v^2 - psi(a) <= 0 on both lines, so both end points clamp
+    // at a (no branch of their own) and I = 0
+    double K = (r - P.dm) * (r + P.dm);
+    double isK = rsq64<NW>(fmax(K, 1e-300));
     cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
     cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
-    if (!(cr > 0.0)) { E.I = 0.0; return; }
+    if (!(cr > 0.0 && K > 0.0)) { E.I = 0.0; return; }
     if (IL == kIlTrapezoid) {
         // (beta - alpha)/2 (Psi(alpha) + Psi(beta)) with Psi = sqrt(K) Delta
         const double cs = fma(E.cb, E.ca, E.sb * E.sa);   // cos(beta/2 - alpha/2)
@@ -678,19 +677,21 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     E.I = 2.0 * K * isK * fma(-nss, ss, es);
 }
 
-// The steps of both end-point angles between consecutive edges, from the sine
-// cr and cosine dt of the half-angle step (negative steps count as zero).  When
-// every active lane of the wave has a small step with dt > 0 the step is
-// 2 asin(cr), with no division; otherwise 2 atan2(cr, dt).
-__device__ __forceinline__ void twice_angles(double cra, double dta, double crb, double dtb, double& da,
-                                             double& db)
+// The steps of both end-point angles between consecutive edges (negative
+// steps count as zero).  The half angles lie in [0, pi/2], so the cosine of a
+// half step is >= 0, and a step whose half-step sine cr is <= 0.05 is 2 asin(cr)
+// by the short series, with no division; unless every active lane of the wave
+// has such steps, 2 atan2(cr, cos).
+__device__ __forceinline__ void angle_steps(const CyEdge& E0, const CyEdge& E1, double& da, double& db)
 {
+    const double cra = fma(E1.sa, E0.ca, -E1.ca * E0.sa), crb = fma(E1.sb, E0.cb, -E1.cb * E0.sb);
     const double ua = fmax(cra, 0.0), ub = fmax(crb, 0.0);
-    if (__all(fmax(ua, ub) <= 0.05 && dta > 0.0 && dtb > 0.0)) {
+    if (__all(fmax(ua, ub) <= 0.05)) {
         da = 2.0 * asin_small(ua);
         db = 2.0 * asin_small(ub);
         return;
     }
+    const double dta = fma(E1.ca, E0.ca, E1.sa * E0.sa), dtb = fma(E1.cb, E0.cb, E1.sb * E0.sb);
     da = cra > 0.0 ? 2.0 * atan2_full(cra, dta) : 0.0;
     db = crb > 0.0 ? 2.0 * atan2_full(crb, dtb) : 0.0;
 }
@@ -706,8 +707,7 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
     for (int m = mb; m <= me; ++m) {
         cy_edge<NW, IL>(q, P, r0 + m, E1);
         double dal, dbe;
-        twice_angles(fma(E1.sa, E0.ca, -E1.ca * E0.sa), fma(E1.ca, E0.ca, E1.sa * E0.sa),
-                     fma(E1.sb, E0.cb, -E1.cb * E0.sb), fma(E1.cb, E0.cb, E1.sb * E0.sb), dal, dbe);
+        angle_steps(E0, E1, dal, dbe);
         // Eq. area_D_l_xi, times J0 = R
         double area = wgt * P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
         sink(m, area);
