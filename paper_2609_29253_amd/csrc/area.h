@@ -648,9 +648,10 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
 {
     // K = r^2 - (R - rho)^2 = 2 R rho + b(r).  K <= 0: the shell misses the
     // surface, r^2 - v^2 - psi(a) <= 0 on both lines, so both end points clamp
-    // at a (no branch of their own) and I = 0
+    // at a (no branch of their own) and I = 0; their Delta (and 1/sqrt K) are
+    // then not finite and not used
     double K = (r - P.dm) * (r + P.dm);
-    double isK = rsq64<NW>(fmax(K, 1e-300));
+    double isK = rsq64<NW>(K);
     cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
     cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
@@ -702,16 +703,26 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
+    const double wR = wgt * P.R;
+    // Eq. area_D_l_xi, times J0 = R, between the edges Ea (inner) and Eb (outer)
+    auto shell = [&](int m, const CyEdge& Ea, const CyEdge& Eb) {
+        double dal, dbe;
+        angle_steps(Ea, Eb, dal, dbe);
+        sink(m, wR * fma(dal, q.d, fma(-q.c, dbe, Eb.I - Ea.I)));
+    };
+    // two shells per trip, the edge records alternating roles (no copies)
     CyEdge E0, E1;
     cy_edge<NW, IL>(q, P, r0 + (mb - 1), E0);
-    for (int m = mb; m <= me; ++m) {
+    int m = mb;
+    for (; m < me; m += 2) {
         cy_edge<NW, IL>(q, P, r0 + m, E1);
-        double dal, dbe;
-        angle_steps(E0, E1, dal, dbe);
-        // Eq. area_D_l_xi, times J0 = R
-        double area = wgt * P.R * fma(dal, q.d, fma(-q.c, dbe, E1.I - E0.I));
-        sink(m, area);
-        E0 = E1;
+        shell(m, E0, E1);
+        cy_edge<NW, IL>(q, P, r0 + (m + 1), E0);
+        shell(m + 1, E1, E0);
+    }
+    if (m == me) {
+        cy_edge<NW, IL>(q, P, r0 + m, E1);
+        shell(m, E0, E1);
     }
 }
 
