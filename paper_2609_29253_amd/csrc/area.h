@@ -61,6 +61,24 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// a * b + c as one three-operand v_fma_f64 with the addend c in a register.
+// Horner steps add a loop-invariant constant; left to itself the compiler
+// copies it into the destination of a two-operand v_fmac_f64, one extra
+// instruction per step.  b is a register too ("v") or, for a constant
+// multiplier, a scalar register ("s").
+__device__ __forceinline__ double fma_vvv(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ double fma_vsv(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // 1/x with a second Newton step (full precision)
 __device__ __forceinline__ double rcp64_full(double x)
 {
@@ -489,26 +507,39 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     const double thr = (TABLE ? 1.0e4 : 35.0) * dev;
     const int itmax = TABLE ? 40 : 12;
     double p2 = 1.0, sumD = 0.0;
-#pragma unroll 1
-    for (int it = 0; it < itmax && thr >= AF; ++it) {
-        double lam = fma(sx, sy, fma(sx, sz, sy * sz));
-        sumD = fma(p2, rcp64(sz * (z + lam)), sumD);
+    if (thr >= AF) {
+        // the first step, with z = sqrt(z) = 1
+        const double lam = fma(sx, sy, sx + sy);
+        z += lam;
+        sumD = rcp64(z);
         x += lam;
         y += lam;
-        z += lam;
         AF += lam;
-        p2 *= 2.0;
+        p2 = 2.0;
         sx = sqrt64_pos<NW>(x);
         sy = sqrt64_pos<NW>(y);
         sz = sqrt64_pos<NW>(z);
+#pragma unroll 1
+        for (int it = 1; it < itmax && thr >= AF; ++it) {
+            double lam = fma(sx, sy, fma(sx, sz, sy * sz));
+            sumD = fma(p2, rcp64(sz * (z + lam)), sumD);
+            x += lam;
+            y += lam;
+            z += lam;
+            AF += lam;
+            p2 *= 2.0;
+            sx = sqrt64_pos<NW>(x);
+            sy = sqrt64_pos<NW>(y);
+            sz = sqrt64_pos<NW>(z);
+        }
     }
     AD = (x + y + 3.0 * z) * 0.2;
     double rAF = rsq64<NW>(AF), iAF = rAF * rAF;
     double X = (AF - x) * iAF, Y = (AF - y) * iAF, Z = -X - Y;
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
     // 1 - E2/10 + E3/14 + E2^2/24 - 3 E2 E3/44 - 5 E2^3/208 + 3 E3^2/104 + E2^2 E3/16
-    double sf = fma(E2, fma(E2, fma(E2, -5.0 / 208.0, 1.0 / 24.0), -0.1), 1.0);
-    sf = fma(E3, fma(E2, fma(E2, 1.0 / 16.0, -3.0 / 44.0), fma(E3, 3.0 / 104.0, 1.0 / 14.0)), sf);
+    double sf = fma(E2, fma_vvv(E2, fma_vsv(E2, -5.0 / 208.0, 1.0 / 24.0), -0.1), 1.0);
+    sf = fma(E3, fma_vvv(E2, fma(E2, 1.0 / 16.0, -3.0 / 44.0), fma_vsv(E3, 3.0 / 104.0, 1.0 / 14.0)), sf);
     double rf = sf * rAF * p2;
     double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
@@ -519,8 +550,8 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     // 1 - 3 D2/14 + D3/6 + 9 D2^2/88 - 3 D4/22 - 9 D2 D3/52 + 3 D5/26 - D2^3/16 + 3 D3^2/40
     //   + 3 D2 D4/20 + 45 D2^2 D3/272 - 9 (D3 D4 + D2 D5)/68, grouped by powers of D2 and D3
     double t2 = fma(D3, 45.0 / 272.0, fma(D2, -1.0 / 16.0, 9.0 / 88.0));
-    t2 = fma(D2, t2, fma(D3, -9.0 / 52.0, fma(D4, 3.0 / 20.0, fma(D5, -9.0 / 68.0, -3.0 / 14.0))));
-    double t3 = fma(D3, 3.0 / 40.0, fma(D4, -9.0 / 68.0, 1.0 / 6.0));
+    t2 = fma(D2, t2, fma(D3, -9.0 / 52.0, fma(D4, 3.0 / 20.0, fma_vsv(D5, -9.0 / 68.0, -3.0 / 14.0))));
+    double t3 = fma(D3, 3.0 / 40.0, fma_vsv(D4, -9.0 / 68.0, 1.0 / 6.0));
     double ser = fma(D2, t2, fma(D3, t3, fma(D4, -3.0 / 22.0, fma(D5, 3.0 / 26.0, 1.0))));
     double rd = fma(p2 * ser * iAD, rAD, 3.0 * sumD);
     if (TABLE) *f_out = s * rf;
