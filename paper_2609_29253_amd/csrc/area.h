@@ -393,7 +393,8 @@ enum : int {
 struct CyQuad {
     double a, b, c, d;
     double sa, ca, sb, cb;          // sin, cos of a/2 and b/2
-    double Dac, Dad, Dbc, Dbd, Da0, Db0;
+    double Qac, Qad, Qbc, Qbd;       // squared corner distances psi(a or b) + (c or d)^2
+    double psia, psib;               // psi(a), psi(b) = (R - rho)^2 + mu sin^2 of the half angle
     double musa2, mucb2;            // mu sin^2(a/2), mu cos^2(b/2)
     int mfirst, mlast;
 };
@@ -444,37 +445,38 @@ __device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, d
     sincos_quarter(0.5 * a, sa, ca);
     sincos_quarter(0.5 * b, sb, cb);
     q.sa = sa; q.ca = ca; q.sb = sb; q.cb = cb;
-    double psia = fma(P.mu * sa, sa, P.dm * P.dm);
-    double psib = fma(P.mu * sb, sb, P.dm * P.dm);
-    q.Dac = sqrt64(psia + c * c);
-    q.Dad = sqrt64(psia + d * d);
-    q.Dbc = sqrt64(psib + c * c);
-    q.Dbd = sqrt64(psib + d * d);
-    q.Da0 = sqrt64(psia);
-    q.Db0 = sqrt64(psib);
+    const double psia = fma(P.mu * sa, sa, P.dm * P.dm);
+    const double psib = fma(P.mu * sb, sb, P.dm * P.dm);
+    q.psia = psia;
+    q.psib = psib;
+    q.Qac = psia + c * c;
+    q.Qad = psia + d * d;
+    q.Qbc = psib + c * c;
+    q.Qbd = psib + d * d;
     q.musa2 = P.mu * sa * sa;
     q.mucb2 = P.mu * cb * cb;
-    q.mfirst = (int)floor(q.Dac - r0) + 1;
-    q.mlast = (int)ceil(q.Dbd - r0);
+    q.mfirst = (int)floor(sqrt64(q.Qac) - r0) + 1;   // nearest and farthest corners
+    q.mlast = (int)ceil(sqrt64(q.Qbd) - r0);
 }
 
 // one end point of the level curve on the line v (Eq. alphabeta), half-angle form;
-// isK = 1/sqrt(r^2 - (R - rho)^2)
+// isK = 1/sqrt(r^2 - (R - rho)^2); Qav, Qbv = psi(a or b) + v^2.  r^2 - Q is
+// one fma: its error is that of the rounded Q, as for (r - sqrt Q)(r + sqrt Q)
 template <int NW>
 __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, double r, double v,
-                                            double Dav, double Dbv, double isK, double& s, double& c,
+                                            double Qav, double Qbv, double isK, double& s, double& c,
                                             double& dl)
 {
-    double qa = (r - Dav) * (r + Dav);          // r^2 - v^2 - psi(a)
+    double qa = fma(r, r, -Qav);                // r^2 - v^2 - psi(a)
     if (!(qa > 0.0)) {
         s = q.sa; c = q.ca;
-        dl = sqrt64<NW>((r - q.Da0) * (r + q.Da0)) * isK;
+        dl = sqrt64<NW>(fma(r, r, -q.psia)) * isK;
         return;
     }
-    double qb = (r - Dbv) * (r + Dbv);          // r^2 - v^2 - psi(b)
+    double qb = fma(r, r, -Qbv);                // r^2 - v^2 - psi(b)
     if (!(qb < 0.0)) {
         s = q.sb; c = q.cb;
-        dl = sqrt64<NW>((r - q.Db0) * (r + q.Db0)) * isK;
+        dl = sqrt64<NW>(fma(r, r, -q.psib)) * isK;
         return;
     }
     s = sqrt64_pos<NW>(qa + q.musa2) * P.isq_mu;   // both arguments > 0 here
@@ -683,8 +685,8 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     // then not finite and not used
     double K = (r - P.dm) * (r + P.dm);
     double isK = rsq64<NW>(K);
-    cy_endpoint<NW>(q, P, r, q.d, q.Dad, q.Dbd, isK, E.sa, E.ca, E.da);
-    cy_endpoint<NW>(q, P, r, q.c, q.Dac, q.Dbc, isK, E.sb, E.cb, E.db);
+    cy_endpoint<NW>(q, P, r, q.d, q.Qad, q.Qbd, isK, E.sa, E.ca, E.da);
+    cy_endpoint<NW>(q, P, r, q.c, q.Qac, q.Qbc, isK, E.sb, E.cb, E.db);
     double cr = fma(E.sb, E.ca, -E.cb * E.sa);   // sin(beta/2 - alpha/2)
     if (!(cr > 0.0 && K > 0.0)) { E.I = 0.0; return; }
     if (IL == kIlTrapezoid) {
