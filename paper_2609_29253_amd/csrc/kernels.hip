@@ -234,7 +234,8 @@ __device__ __forceinline__ double wrap_pi(double u)
 
 // The interval ends of the folded quadrants live in LDS (one column per thread,
 // kBoxSlots doubles), read back per quadrant: kept in registers they would be
-// live through every sweep and pushed to scratch memory at three waves per SIMD.
+// live through every sweep and pushed to scratch memory at three or four waves
+// per SIMD.
 constexpr int kBoxSlots = 8;
 
 // MERGE of the folded intervals holds for every I_l that is a difference of a
@@ -326,8 +327,8 @@ struct CylinderPair {
 };
 
 // Cylinder areas are FP64 in both variants.  With FP32 input and output the
-// elliptic differences need ~1e-12, and one Newton step after v_rsq_f64
-// (relative error 2^-48) is enough; the FP64 variant takes two.
+// elliptic differences need ~1e-12, and one correction step after v_rsq_f64 /
+// v_rcp_f64 (relative error 2^-48) is enough; the FP64 variant takes two.
 template <class Real> struct CylNewton { static constexpr int value = 2; };
 template <> struct CylNewton<float> { static constexpr int value = 1; };
 
