@@ -125,7 +125,10 @@ __device__ __forceinline__ double sqrt64(double x)
     return sqrt64_pos<NEWTON>(fmax(x, 1e-300));
 }
 
-__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(fmaxf(x, 0.0f)); }
+// FP32 square root as the one v_sqrt_f32 (1 ulp); the IEEE-rounded sqrtf the
+// compiler emits otherwise adds a denormal rescale and a correction step
+// (some 15 instructions)
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 0.0f)); }
 __device__ __forceinline__ double sqrt_t(double x) { return x > 0.0 ? x * rsq64(x) : 0.0; }
 // atan2 for y, x >= 0.  Small angles (y <= x/5) take the odd Taylor series of
 // atan(y/x), whose error is the rounding of a few correctly rounded operations;
@@ -172,7 +175,7 @@ template <> struct AtanMx<float> {
         if (x > 4.0f) return atanf(x) - x;
         float acc = 0.0f, scale = 1.0f;
         for (int i = 0; i < 4 && x >= 0.1f; ++i) {
-            float q = 1.0f + __builtin_sqrtf(fmaf(x, x, 1.0f));
+            float q = 1.0f + __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
             float iq = __builtin_amdgcn_rcpf(q);
             acc = fmaf(-scale * x * x * x, iq * iq, acc);
             x *= iq;
