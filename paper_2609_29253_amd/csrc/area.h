@@ -166,7 +166,9 @@ __device__ __forceinline__ T sdiv(T n, T d)
 
 // atan(x) - x for x >= 0 without cancellation: halving
 //   atan x - x = 2 (atan y - y) - x^3 / (1 + sqrt(1 + x^2))^2,  y = x / (1 + sqrt(1 + x^2)),
-// then the Taylor series of atan y - y.
+// then the Taylor series of atan y - y, through y^13; its relative truncation
+// error is ~0.2 y^12: below 1.2e-8 (FP32) from y < 0.25, below 2e-13 (the
+// FP64 series runs to y^23) from y < 0.1.
 template <class T> struct AtanMx;
 
 template <> struct AtanMx<float> {
@@ -174,7 +176,7 @@ template <> struct AtanMx<float> {
     {
         if (x > 4.0f) return atanf(x) - x;
         float acc = 0.0f, scale = 1.0f;
-        for (int i = 0; i < 4 && x >= 0.1f; ++i) {
+        for (int i = 0; i < 4 && x >= 0.25f; ++i) {
             float q = 1.0f + __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
             float iq = __builtin_amdgcn_rcpf(q);
             acc = fmaf(-scale * x * x * x, iq * iq, acc);
