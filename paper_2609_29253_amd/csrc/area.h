@@ -546,7 +546,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double E2 = fma(X, Y, -Z * Z), E3 = X * Y * Z;
     // 1 - E2/10 + E3/14 + E2^2/24 - 3 E2 E3/44 - 5 E2^3/208 + 3 E3^2/104 + E2^2 E3/16
     double sf = fma(E2, fma_vvv(E2, fma_vsv(E2, -5.0 / 208.0, 1.0 / 24.0), -0.1), 1.0);
-    sf = fma(E3, fma_vvv(E2, fma(E2, 1.0 / 16.0, -3.0 / 44.0), fma_vsv(E3, 3.0 / 104.0, 1.0 / 14.0)), sf);
+    sf = fma(E3, fma_vvv(E2, fma_vsv(E2, 1.0 / 16.0, -3.0 / 44.0), fma_vsv(E3, 3.0 / 104.0, 1.0 / 14.0)), sf);
     double rf = sf * rAF * p2;
     double rAD = rsq64<NW>(AD), iAD = rAD * rAD;
     X = (AD - x) * iAD;
@@ -556,13 +556,13 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     double D2 = XY - 6.0 * Z2, D3 = (3.0 * XY - 8.0 * Z2) * Z, D4 = 3.0 * (XY - Z2) * Z2, D5 = XY * Z2 * Z;
     // 1 - 3 D2/14 + D3/6 + 9 D2^2/88 - 3 D4/22 - 9 D2 D3/52 + 3 D5/26 - D2^3/16 + 3 D3^2/40
     //   + 3 D2 D4/20 + 45 D2^2 D3/272 - 9 (D3 D4 + D2 D5)/68, grouped by powers of D2 and D3
-    double t2 = fma(D3, 45.0 / 272.0, fma(D2, -1.0 / 16.0, 9.0 / 88.0));
+    double t2 = fma(D3, 45.0 / 272.0, fma_vsv(D2, -1.0 / 16.0, 9.0 / 88.0));
     t2 = fma(D2, t2, fma(D3, -9.0 / 52.0, fma(D4, 3.0 / 20.0, fma_vsv(D5, -9.0 / 68.0, -3.0 / 14.0))));
     double t3 = fma(D3, 3.0 / 40.0, fma_vsv(D4, -9.0 / 68.0, 1.0 / 6.0));
     double ser = fma(D2, t2, fma(D3, t3, fma(D4, -3.0 / 22.0, fma(D5, 3.0 / 26.0, 1.0))));
     double rd = fma(p2 * ser * iAD, rAD, 3.0 * sumD);
     if (TABLE) *f_out = s * rf;
-    return s * rf - (nu * (1.0 / 3.0)) * s * s * s * rd;
+    return s * fma(-(nu * (1.0 / 3.0)) * (s * s), rd, rf);
 }
 
 // ---------------------------------------------------------------------------
