@@ -500,12 +500,13 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // fixed initial deviation, and the factors 2^n that the scaling leaves on
 // R_F and on the R_D series are applied once at the end.  With c^2, D^2 <= 1
 // = z, z stays the largest argument, so A_D = (x + y + 3z)/5 >= A_F = (x + y
-// + z)/3 and the test needs A_F only.  x and y start at >= 1e-300, so every
-// square root in the loop has a positive argument.
+// + z)/3 and the test needs A_F only.  x and y start at c^2 + 1e-300 and D^2 +
+// 1e-300 (the same values unless they are below 1e-284), so every square root
+// in the loop has a positive argument.
 template <int NW, bool TABLE = false>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu, double* f_out = nullptr)
 {
-    double x = fmax(c * c, 1e-300), y = fmax(dl * dl, 1e-300), z = 1.0;
+    double x = fma(c, c, 1e-300), y = fma(dl, dl, 1e-300), z = 1.0;
     double sx = fabs(c), sy = dl, sz = 1.0;
     double AF = (x + y + z) * (1.0 / 3.0);
     double AD = (x + y + 3.0 * z) * 0.2;
@@ -660,7 +661,7 @@ __device__ __forceinline__ double asin_small(double u)
 __device__ __forceinline__ double atan_unit(double t)
 {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t *= rcp64_full(1.0 + sqrt64(fma(t, t, 1.0)));
+    for (int i = 0; i < 4; ++i) t *= rcp64_full(1.0 + sqrt64_pos(fma(t, t, 1.0)));
     const double y = t * t, y2 = y * y, y3 = y2 * y;
     const double p = 45045.0 - 15015.0 * y + 9009.0 * y2 - 6435.0 * y3 + 5005.0 * (y2 * y2) -
                      4095.0 * (y2 * y3) + 3465.0 * (y3 * y3);
