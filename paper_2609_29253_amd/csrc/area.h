@@ -384,7 +384,7 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
 // ---------------------------------------------------------------------------
 
 struct CyPair {
-    double R, dm, mu, isq_mu;    // radius, |R - rho|, 4 R rho, 1/sqrt(mu) (0 when rho = 0)
+    double R, dm, mu, imu;       // radius, |R - rho|, 4 R rho, 1/mu (0 when rho = 0)
     const double2* lut;          // E~, F~ tables (lookup-table I_l only)
 };
 
@@ -400,7 +400,7 @@ struct CyQuad {
     double sa, ca, sb, cb;          // sin, cos of a/2 and b/2
     double Qac, Qad, Qbc, Qbd;       // squared corner distances psi(a or b) + (c or d)^2
     double psia, psib;               // psi(a), psi(b) = (R - rho)^2 + mu sin^2 of the half angle
-    double musa2, mucb2;            // mu sin^2(a/2), mu cos^2(b/2)
+    double sa2, cb2;                // sin^2(a/2), cos^2(b/2)
     int mfirst, mlast;
 };
 
@@ -458,8 +458,8 @@ __device__ __forceinline__ void cy_setup(CyQuad& q, const CyPair& P, double a, d
     q.Qad = psia + d * d;
     q.Qbc = psib + c * c;
     q.Qbd = psib + d * d;
-    q.musa2 = P.mu * sa * sa;
-    q.mucb2 = P.mu * cb * cb;
+    q.sa2 = sa * sa;
+    q.cb2 = cb * cb;
     q.mfirst = (int)floor(sqrt64(q.Qac) - r0) + 1;   // nearest and farthest corners
     q.mlast = (int)ceil(sqrt64(q.Qbd) - r0);
 }
@@ -484,8 +484,9 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
         dl = sqrt64<NW>(fma(r, r, -q.psib)) * isK;
         return;
     }
-    s = sqrt64_pos<NW>(qa + q.musa2) * P.isq_mu;   // both arguments > 0 here
-    c = sqrt64_pos<NW>(q.mucb2 - qb) * P.isq_mu;
+    // sin^2 = (qa + mu sa^2) / mu and cos^2 = (mu cb^2 - qb) / mu, both > 0 here
+    s = sqrt64_pos<NW>(fma(qa, P.imu, q.sa2));
+    c = sqrt64_pos<NW>(fma(-qb, P.imu, q.cb2));
     dl = v * isK;
 }
 

@@ -265,7 +265,7 @@ struct CylinderPair {
         P.R = R;
         P.dm = fabs(R - rho);
         P.mu = 4.0 * R * rho;
-        P.isq_mu = P.mu > 0.0 ? rsq64(P.mu) : 0.0;
+        P.imu = P.mu > 0.0 ? rcp64_full(P.mu) : 0.0;
         double u1 = wrap_pi(-th - thi), u2 = wrap_pi(th - thi);
         // Eq. folded_intervals (merged where the areas are exact, see split_at_zero)
         if (u1 < 0.0 && 0.0 < u2) {
