@@ -32,8 +32,8 @@ METRIC = "A+Aᵀ voxel×transducer pairs/s, closed-form FP32 vs quadrature/FP64 
 FLOPS_PER_EVAL = {
     ("closed", 0, "fp32"): 106.0,   # planar, FP32 cancellation-free form (static count of the common path)
     ("closed", 0, "fp64"): 106.0,
-    ("closed", 1, "fp32"): 282.4,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
-    ("closed", 1, "fp64"): 337.2,   # cylinder, two Newton steps
+    ("closed", 1, "fp32"): 282.3,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
+    ("closed", 1, "fp64"): 337.1,   # cylinder, two Newton steps
 }
 # per surface point of the quadrature (FP64 distance + bin test, FP32/FP64 weight)
 FLOPS_PER_POINT = 14.0
