@@ -54,7 +54,7 @@ typedef enum {
     PAT_E_STATE = 6,       /* forward/adjoint before set_geometry               */
     PAT_E_DEVICE = 7,      /* a HIP call failed (text in pat_last_error)        */
     PAT_E_OOM = 8,         /* device allocation failed                          */
-    PAT_E_UNSUPPORTED = 9  /* valid request this build does not implement       */
+    PAT_E_UNSUPPORTED = 9  /* valid request the library does not support      */
 } pat_status;
 
 enum { PAT_PLANAR = 0, PAT_CYLINDER = 1 };
