@@ -7,7 +7,7 @@ Prints one JSON line (rank 0) with the A+A^T voxel x transducer pair rate,
 the roofline of the dominant kernel and the FP64 oracle's rate on the host
 cores for a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg2] [--no-variants] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload cyl256_128c] [--no-variants] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -80,16 +80,8 @@ def log(*a):
 
 def build_workload(name):
     import pat_inputs as P
-    if name == "cfg1":
-        return P.config1()
-    if name == "cfg2":
-        return P.config2()
-    if name == "cfg3":
-        return P.config3()
-    if name == "cfg5":
-        return P.config5()
-    if name == "cfg4":
-        return P.config4_pgd()
+    if name in P.WORKLOADS:
+        return P.WORKLOADS[name]()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -171,7 +163,7 @@ def run_next(args, prob, kern, B, pairs, torch, dev, log):
         log(f"[bench] next quadrature {qn}x{qn}: {rows[f'quadrature_{qn}x{qn}_fp32']}")
     prob.quad_n = q0
     # coarse area grid (Remark 1) at U = 4: every fine bin vs one area per native sample
-    p4 = P.config2(U=4)
+    p4 = P.cyl256_128c(U=4)
     k4 = build_kernel(p4.phi_type, p4.kappa, p4.eir, p4.sound_speed, p4.fs, p4.U)
     h4, nf4 = O.kernel_of(p4)
     ex4 = (O.forward(p4, ksub=ks, kernel=(h4, nf4)), O.adjoint(p4, vsub=vs, kernel=(h4, nf4)))
@@ -285,7 +277,7 @@ def run_cpu_table(torch, dev, log):
     from paper_2609_29253_amd.operator import PatOperator
     rows = {}
     threads = O.num_threads()
-    for name in ("cfg1", "cfg2", "cfg3", "cfg5"):
+    for name in ("planar64_32c", "cyl256_128c", "planar512_256c", "batch8_planar256_128c"):
         prob = build_workload(name)
         B = prob.coef.shape[0]
         op = PatOperator.from_problem(prob, mode="closed", precision="fp32", max_batch=B)
@@ -310,7 +302,7 @@ def run_cpu_table(torch, dev, log):
                     "a_plus_at_pairs_per_s": 1.0 / (1.0 / fw + 1.0 / ad),
                     "sample": f"A on {nk} transducers over all voxels ({tf:.1f}s), A^T on {nv} voxels ({ta:.1f}s)"}
 
-        small = prob.N * prob.K < 5e7          # cfg1: every transducer, more voxels
+        small = prob.N * prob.K < 5e7          # planar64_32c: every transducer, more voxels
         r_all = rates(prob.K if small else threads, 4096 if small else 1024)
         O.set_threads(1)
         r_one = rates(prob.K if small else 1, 1024 if small else 256)
@@ -327,7 +319,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cyl256_128c")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib", action="store_true",
@@ -347,7 +339,7 @@ def main():
                     help="only the LIB-scale rows (sparse forward at U = 61, dense A + A^T at U = 11 on a "
                          "sub-scan), printed as one JSON object instead of the benchmark line")
     ap.add_argument("--cpu-table", action="store_true",
-                    help="only the per-configuration GPU and oracle rates (cfg1, cfg2, cfg3, cfg5), printed as one "
+                    help="only the per-configuration GPU and oracle rates (planar64_32c, cyl256_128c, planar512_256c, batch8_planar256_128c), printed as one "
                          "JSON object instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

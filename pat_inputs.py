@@ -440,15 +440,15 @@ def _finish(name, tr, grid, fs, L, coef, ydraw_seed=None, U=1, quad=(16, 16), me
     return p
 
 
-def config1(U: int = 1) -> Problem:
+def planar64_32c(U: int = 1) -> Problem:
     """32^3 grid (0.1 mm), 64 planar 1x1 mm on a Fibonacci sphere of radius
     20 mm, fs 40 MHz, L 512; U[0,1) coefficients inside a 1.2 mm ball."""
     grid = Grid.centred(32, 0.1e-3)
     tr = facing_planar_array(fibonacci_points(64, 20e-3), 0.5e-3, 0.5e-3)
-    return _finish("cfg1_planar64_32c", tr, grid, 40e6, 512, ball_uniform(grid, 1.2e-3, 0), 1, U=U)
+    return _finish("planar64_32c", tr, grid, 40e6, 512, ball_uniform(grid, 1.2e-3, 0), 1, U=U)
 
 
-def config2(n: int = 128, U: int = 1) -> Problem:
+def cyl256_128c(n: int = 128, U: int = 1) -> Problem:
     """128^3 grid (0.1 mm), 256 cylinders (6 mm curved x 3 mm straight,
     R = 25 mm) on a 180-degree arc of radius 40 mm, 16 elements x 16 rotations;
     fs 50 MHz, L 2048; 200 Gaussian blobs + 16 polylines (seed 0); fine grid
@@ -457,39 +457,39 @@ def config2(n: int = 128, U: int = 1) -> Problem:
     tr = arc_cylinder_array(16, 16, 40e-3, 25e-3, 6e-3, 3e-3)
     rng = np.random.default_rng(0)
     coef = blobs(grid, rng, 200) + polylines(grid, rng, 16)
-    name = "cfg2_cyl256_128c" if U == 1 else f"cfg2_cyl256_128c_U{U}"
+    name = "cyl256_128c" if U == 1 else f"cyl256_128c_U{U}"
     return _finish(name, tr, grid, 50e6, 2048, coef, 1, U=U)
 
 
-def config3(n: int = 256) -> Problem:
+def planar512_256c(n: int = 256) -> Problem:
     """256^3 grid (0.08 mm), 512 planar 0.5x3 mm on a Fibonacci hemisphere of
     radius 50 mm, fs 50 MHz, L 4096; U[0,1) coefficients, N(0,1) signals."""
     grid = Grid.centred(n, 0.08e-3)
     tr = hemisphere_planar_array(512, 50e-3, 0.25e-3, 1.5e-3)
-    return _finish("cfg3_planar512_256c", tr, grid, 50e6, 4096, uniform(grid, 0), 1)
+    return _finish("planar512_256c", tr, grid, 50e6, 4096, uniform(grid, 0), 1)
 
 
-def config4_fd() -> Problem:
+def fd_cyl8_10c() -> Problem:
     """10^3 grid (0.1 mm) with 8 cylinders of the 24x16 arc array, for the
     finite-difference check of the autograd wrapper."""
     grid = Grid.centred(10, 0.1e-3)
     full = arc_cylinder_array(24, 16, 40e-3, 25e-3, 6e-3, 3e-3)
     tr = full.subset(np.arange(0, full.K, full.K // 8)[:8])
-    return _finish("cfg4fd_cyl8_10c", tr, grid, 50e6, 2048, uniform(grid, 3), 4)
+    return _finish("fd_cyl8_10c", tr, grid, 50e6, 2048, uniform(grid, 3), 4)
 
 
-def config4_pgd(n: int = 192) -> Problem:
+def pgd_cyl384_192c(n: int = 192) -> Problem:
     """192^3 grid (0.1 mm), 384 cylinders (24 elements x 16 rotations), fs
     50 MHz, L 2048; ground truth = 24 polylines (seed 5)."""
     grid = Grid.centred(n, 0.1e-3)
     tr = arc_cylinder_array(24, 16, 40e-3, 25e-3, 6e-3, 3e-3)
     truth = polylines(grid, np.random.default_rng(5), 24)
-    p = _finish("cfg4pgd_cyl384_192c", tr, grid, 50e6, 2048, truth, None)
+    p = _finish("pgd_cyl384_192c", tr, grid, 50e6, 2048, truth, None)
     p.meta.update(noise_seed=6, power_seed=7, noise_level=0.01, iterations=50)
     return p
 
 
-def config5(n: int = 128, B: int = 8) -> Problem:
+def batch8_planar256_128c(n: int = 128, B: int = 8) -> Problem:
     """B = 8 volumes on a 128^3 grid (0.1 mm), U[0,1) coefficients inside
     centred balls of sorted random radii in [0.5, 3] mm; 256 planar 1x1 mm on a
     Fibonacci sphere of radius 40 mm; fs 50 MHz, L 2048."""
@@ -497,7 +497,7 @@ def config5(n: int = 128, B: int = 8) -> Problem:
     tr = facing_planar_array(fibonacci_points(256, 40e-3), 0.5e-3, 0.5e-3)
     radii = np.sort(np.random.default_rng(8).uniform(0.5e-3, 3e-3, size=B))
     coef = np.stack([ball_uniform(grid, float(radii[b]), 9 + b) for b in range(B)])
-    p = _finish("cfg5_batch8_planar256_128c", tr, grid, 50e6, 2048, coef, 1)
+    p = _finish("batch8_planar256_128c", tr, grid, 50e6, 2048, coef, 1)
     p.meta["radii"] = [float(r) for r in radii]
     return p
 
@@ -544,4 +544,6 @@ def small_case(shape: int = PLANAR, n: int = 6, K: int = 4, L: int = 160, fs: fl
     return p
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4_pgd, 5: config5}
+# the full-size workloads by name (each name states its array and grid)
+WORKLOADS = {f.__name__: f for f in (planar64_32c, cyl256_128c, planar512_256c, pgd_cyl384_192c,
+                                      batch8_planar256_128c)}

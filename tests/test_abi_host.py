@@ -72,7 +72,7 @@ def test_kernel_builder_rejects_bad_arguments():
 def test_geometry_validation():
     from paper_2609_29253_amd import _lib
     from paper_2609_29253_amd.operator import check_geometry
-    p = P.config1()
+    p = P.planar64_32c()
     g = (p.grid.n, p.grid.origin, p.grid.spacing)
     d = check_geometry(p.tr.packed, *g, p.kappa)
     assert 15e-3 < d < 20e-3
@@ -91,7 +91,7 @@ def test_geometry_validation():
     with pytest.raises(_lib.PatError) as e:
         check_geometry(bad, *g, p.kappa)
     assert e.value.status == 4
-    cyl = P.config4_fd().tr.packed.copy()
+    cyl = P.fd_cyl8_10c().tr.packed.copy()
     cyl[0, 13] = math.pi / 2                   # theta_max must be < pi/2
     with pytest.raises(_lib.PatError) as e:
         check_geometry(cyl, (10, 10, 10), (-0.45e-3,) * 3, 0.1e-3, 0.15e-3)

@@ -32,7 +32,7 @@ _cache = {}
 
 def problem(name):
     if name not in _cache:
-        p = {"cfg2": P.config2, "cfg3": P.config3, "cfg5": P.config5}[name]()
+        p = {"cyl256_128c": P.cyl256_128c, "planar512_256c": P.planar512_256c, "batch8_planar256_128c": P.batch8_planar256_128c}[name]()
         _cache[name] = {"p": p}
     return _cache[name]
 
@@ -63,7 +63,7 @@ def gpu_full(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("name,ks", [("cfg2", [0, 131]), ("cfg3", [0, 300]), ("cfg5", [0, 77])])
+@pytest.mark.parametrize("name,ks", [("cyl256_128c", [0, 131]), ("planar512_256c", [0, 300]), ("batch8_planar256_128c", [0, 77])])
 def test_fullsize_sampled_parity(gpu, name, ks, prec):
     p, (s, z) = gpu_full(name, prec)
     vs = np.linspace(0, p.N - 1, 3000).astype(np.int64)

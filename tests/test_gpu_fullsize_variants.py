@@ -20,7 +20,7 @@ _cache = {}
 
 def _problem(U):
     if U not in _cache:
-        _cache[U] = P.config2() if U == 1 else P.config2(U=U)
+        _cache[U] = P.cyl256_128c() if U == 1 else P.cyl256_128c(U=U)
     return _cache[U]
 
 

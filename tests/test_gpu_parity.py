@@ -62,16 +62,16 @@ def test_small_parity(gpu, case, prec, mode):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_config1_full(gpu, prec):
+def test_planar64_32c_full(gpu, prec):
     """Planar 64 x 32^3, every output against the oracle, plus the dot test."""
-    p = P.config1()
+    p = P.planar64_32c()
     s_ref = O.forward(p)
     z_ref = O.adjoint(p)
     s, z = run_gpu(p, "closed", prec)
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
     lhs, rhs = float(np.sum(s * p.y)), float(np.sum(z * p.coef))
     gap = abs(lhs - rhs) / (np.linalg.norm(s) * np.linalg.norm(p.y))
-    print(f"cfg1 {prec}: forward {es:.3e} adjoint {ez:.3e} normalised dot gap {gap:.3e}", flush=True)
+    print(f"planar64_32c {prec}: forward {es:.3e} adjoint {ez:.3e} normalised dot gap {gap:.3e}", flush=True)
     assert es < TOL[prec] and ez < TOL[prec]
     assert gap < (1e-6 if prec == "fp32" else 1e-13)
 

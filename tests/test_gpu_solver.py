@@ -24,7 +24,7 @@ DT = {"fp32": torch.float32, "fp64": torch.float64}
 
 
 def fd_problem():
-    return P.config4_fd()
+    return P.fd_cyl8_10c()
 
 
 @pytest.mark.parametrize("prec,ncoord,eps,tol", [("fp64", 1000, 1.0, 1e-10), ("fp32", 100, 10.0, 1e-4)])
@@ -66,9 +66,9 @@ def test_autograd_matches_central_differences(gpu, prec, ncoord, eps, tol):
 
 
 def pgd_problem():
-    full = P.config4_pgd(n=48)
+    full = P.pgd_cyl384_192c(n=48)
     tr = full.tr.subset(np.arange(0, full.K, 8))
-    return dataclasses.replace(full, tr=tr, name="cfg4pgd_cyl48_48c")
+    return dataclasses.replace(full, tr=tr, name="pgd_cyl48_48c")
 
 
 def test_projected_gradient_monotone_and_resumable(gpu):
