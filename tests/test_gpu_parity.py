@@ -41,6 +41,9 @@ SMALL = [
     (P.PLANAR, 3, 2, 9, 4, 200),
     (P.CYLINDER, 1, 1, 13, 5, 260),
     (P.CYLINDER, 2, 3, 9, 4, 260),
+    # five to eight volumes: the kernels instantiated for eight right-hand sides
+    (P.PLANAR, 2, 5, 7, 3, 200),
+    (P.CYLINDER, 1, 6, 7, 3, 260),
 ]
 
 
