@@ -352,6 +352,124 @@ def test_point_transducer_limit():
         assert rel_l2(fp_, fs_) < 2e-3
 
 
+def _rotated_frame(seed):
+    """Orthonormal e1, e2 of a random orientation and their normal e1 x e2."""
+    q, _ = np.linalg.qr(np.random.default_rng(seed).normal(size=(3, 3)))
+    return q[:, 0], q[:, 1], np.cross(q[:, 0], q[:, 1])
+
+
+@pytest.mark.parametrize("shape", [P.PLANAR, P.CYLINDER])
+def test_quadrature_points_are_cell_centres_on_the_surface(shape):
+    """Alg. 2 with the tensor midpoint rule (Prop. 2: barycentres of equal
+    cells of the parameter rectangle D): every point lies on the surface of
+    Eq. plane_param / Eq. cylinder_param, the points are exactly the cell
+    centres of the n1 x n2 partition of D, each once, and Q dA is the area of
+    the surface (R 2 theta_max 2 L_z for the cylinder, whose area element is
+    R du dv)."""
+    e1, e2, n3 = _rotated_frame(5 + shape)
+    c0 = np.array([1.3e-3, -2.1e-3, 0.7e-3])
+    n1, n2 = 7, 5
+    if shape == P.PLANAR:
+        L1, L2 = 0.6e-3, 0.35e-3
+        tr = P.planar(c0, e1, e2, L1, L2)
+        area = 4 * L1 * L2
+    else:
+        R, th, Lz = 9e-3, 0.37, 1.2e-3
+        tr = P.cylinder(c0, e1, e2, R, th, Lz)
+        area = 2 * th * R * 2 * Lz
+    pts, dA = O.quad_points(tr, n1, n2)
+    assert pts.shape == (n1 * n2, 3)
+    assert n1 * n2 * dA == pytest.approx(area, rel=1e-14)
+    d = pts - c0
+    if shape == P.PLANAR:
+        u, v = d @ e1, d @ e2
+        assert np.max(np.abs(d @ n3)) < 1e-15            # in the plane of the rectangle
+        cu = -L1 + (np.arange(n1) + 0.5) * 2 * L1 / n1
+        cv = -L2 + (np.arange(n2) + 0.5) * 2 * L2 / n2
+    else:
+        z = d @ e1
+        radial = d - np.outer(z, e1)
+        # on the cylinder of radius R about the focal line through c0 along e1
+        assert np.max(np.abs(np.linalg.norm(radial, axis=1) / R - 1.0)) < 1e-14
+        # angle from e2 about the axis; the sign of e1 x e2 is immaterial
+        # (reading 13), so the cell centres are compared up to that sign
+        u = np.arctan2(radial @ n3, radial @ e2)
+        v = z
+        assert np.max(np.abs(u)) < th
+        cu = -th + (np.arange(n1) + 0.5) * 2 * th / n1
+        cv = -Lz + (np.arange(n2) + 0.5) * 2 * Lz / n2
+    grid = {(a, b) for a in range(n1) for b in range(n2)}
+    got = set()
+    for uu, vv in zip(u, v):
+        a = int(np.argmin(np.abs(cu - uu)))
+        b = int(np.argmin(np.abs(cv - vv)))
+        assert abs(cu[a] - uu) < 1e-12 * max(1.0, abs(cu[0])) and abs(cv[b] - vv) < 1e-15
+        got.add((a, b))
+    assert got == grid
+
+
+@pytest.mark.parametrize("shape", [P.PLANAR, P.CYLINDER])
+def test_single_voxel_point_transducer_limit_is_exact(shape):
+    """One voxel and a transducer far below one radial step: its whole
+    surface falls in the bin m holding the distance r to the surface centre,
+    and the two methods reduce to their definitions (Eq. ui_area,
+    Eq. def_f_point): the surface coefficient is U F_s |Sigma| / (c tau_{m-1/2})
+    exactly and the point coefficient U F_s sum_j dA_j / r_j tends to
+    U F_s |Sigma| / r (second order in the patch size with centred points).
+    A misplaced point set (another part of the cylinder, the axis or the
+    back of the focal line) lands in another bin; a cell area without the
+    cylinder's R scales the value."""
+    p = P.small_case(shape, n=1, K=3, L=300)
+    p.coef = np.ones((1, 1))
+    tr = p.tr.packed
+    if shape == P.CYLINDER:
+        tr[:, 13], tr[:, 14] = 2e-5, 1.5e-7
+        area = 2 * tr[:, 13] * tr[:, 12] * 2 * tr[:, 14]
+        centre = tr[:, 1:4] + tr[:, 12:13] * tr[:, 7:10]   # surface point at angle 0
+    else:
+        tr[:, 10], tr[:, 11] = 2e-7, 1.5e-7
+        area = 4 * tr[:, 10] * tr[:, 11]
+        centre = tr[:, 1:4]
+    p.quad_n = (2, 2)
+    h, nf = O.kernel_of(p)
+    ufs, c = p.U * p.fs, p.sound_speed
+    for k in range(p.K):
+        f_surf, Mlo = O.fcoef(p, k, mode=O.MODE_SURFACE, kernel=(h, nf))
+        f_pt, Mlo2 = O.fcoef(p, k, mode=O.MODE_POINT, kernel=(h, nf))
+        assert Mlo == Mlo2
+        nz_s, nz_p = np.nonzero(f_surf[0])[0], np.nonzero(f_pt[0])[0]
+        assert len(nz_s) == 1 and np.array_equal(nz_s, nz_p)
+        m = Mlo + int(nz_s[0])
+        r = float(np.linalg.norm(centre[k] - np.asarray(p.grid.origin)))
+        assert c * (p.t0 + (m - 1) / ufs) <= r < c * (p.t0 + m / ufs)     # bin rule of Alg. 2
+        assert f_surf[0, nz_s[0]] == pytest.approx(ufs * area[k] / (c * (p.t0 + (m - 0.5) / ufs)), rel=1e-10)
+        assert f_pt[0, nz_p[0]] == pytest.approx(ufs * area[k] / r, rel=1e-9)
+
+
+def test_cylinder_point_method_converges_to_surface_method():
+    """Prop. 2 on the cylinder (Sec. 4.2 parametrisation): with the bin grid
+    fixed, the point method's coefficients tend to the exact cell averages of
+    1/r, which the surface method equals up to its midpoint rule (~1e-7 here),
+    so the signals converge to the surface method's.  While the smooth part of
+    the quadrature error dominates, it falls as Q^-1 (a factor ~4 per doubling
+    of n1 = n2); later the arrival-time jumps between bins slow it.  A
+    left-point rule (first order, a factor ~2), points on the wrong side of the
+    focal line or a cell area without R do not converge to it."""
+    p = P.small_case(P.CYLINDER, n=3, K=2, L=300, U=4)
+    h, nf = O.kernel_of(p)
+    s_surf = O.forward(p, kernel=(h, nf))
+    qs = [2, 4, 8, 16, 32, 64, 128]
+    errs = []
+    for q in qs:
+        p.quad_n = (q, q)
+        errs.append(rel_l2(O.forward(p, mode=O.MODE_POINT, kernel=(h, nf)), s_surf))
+    for a, b in zip(errs[:3], errs[1:4]):
+        assert a / b > 3.0, errs
+    slope = np.polyfit(np.log(np.array(qs, dtype=float) ** 2), np.log(errs), 1)[0]
+    assert slope < -0.6, (slope, errs)
+    assert errs[-1] < 2e-3
+
+
 # ---------------------------------------------------------------------------
 # operator identities
 # ---------------------------------------------------------------------------
