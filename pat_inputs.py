@@ -426,16 +426,16 @@ def window_end_bound(tr: Transducers, grid: Grid, kappa: float, c: float) -> flo
 # ----------------------------------------------------------------------------
 
 def _finish(name, tr, grid, fs, L, coef, ydraw_seed=None, U=1, quad=(16, 16), meta=None,
-            phi=PHI_WENDLAND2, kappa_factor=1.5, B=None):
+            phi=PHI_WENDLAND2, kappa_factor=1.5, B=None, c=SOUND_SPEED):
     kappa = kappa_factor * grid.spacing
     eir = Eir.gauss_cos()
-    t0 = window_start(tr, grid, kappa, SOUND_SPEED, fs)
+    t0 = window_start(tr, grid, kappa, c, fs)
     coef = np.atleast_2d(np.asarray(coef, dtype=np.float64))
     y = None
     if ydraw_seed is not None:
         y = np.random.default_rng(ydraw_seed).normal(size=(coef.shape[0], tr.K, L))
-    p = Problem(name, tr, grid, phi, kappa, eir, SOUND_SPEED, fs, L, U, t0, quad, coef, y, meta or {})
-    end = window_end_bound(tr, grid, kappa, SOUND_SPEED) / SOUND_SPEED + eir.te
+    p = Problem(name, tr, grid, phi, kappa, eir, c, fs, L, U, t0, quad, coef, y, meta or {})
+    end = window_end_bound(tr, grid, kappa, c) / c + eir.te
     p.meta["window_covers_signal"] = bool(end <= t0 + L / fs)
     return p
 
@@ -541,6 +541,53 @@ def small_case(shape: int = PLANAR, n: int = 6, K: int = 4, L: int = 160, fs: fl
     coef = rng.random((B, grid.N))
     p = _finish(f"small_{'pl' if shape == PLANAR else 'cy'}{K}_{n}c", tr, grid, fs, L, coef,
                 seed + 1, U=U, phi=phi)
+    return p
+
+
+def mixed_case(n: int = 7, K_planar: int = 3, K_cyl: int = 3, L: int = 300, fs: float = 40e6, U: int = 1,
+               seed: int = 0, B: int = 1) -> Problem:
+    """Planar and cylindrical transducers in one array: the planar rectangles of
+    ``small_case`` interleaved with the cylinders of its cylinder array (same
+    irrational radius factor), so that transducer indices of the two shapes
+    alternate."""
+    pl = small_case(PLANAR, n=n, K=K_planar, L=L, fs=fs, U=U, seed=seed, B=B).tr.packed
+    cy = small_case(CYLINDER, n=n, K=K_cyl, L=L, fs=fs, U=U, seed=seed, B=B).tr.packed
+    rows = []
+    for j in range(max(len(pl), len(cy))):
+        if j < len(pl):
+            rows.append(pl[j])
+        if j < len(cy):
+            rows.append(cy[j])
+    tr = Transducers(np.array(rows))
+    grid = Grid.centred(n, 0.1e-3)
+    coef = np.random.default_rng(seed).random((B, grid.N))
+    return _finish(f"mixed_pl{K_planar}_cy{K_cyl}_{n}c", tr, grid, fs, L, coef, seed + 1, U=U)
+
+
+def exact_tie_case(n: int = 7, height: int = 320, L: int = 200) -> Problem:
+    """Point-method distances that fall exactly on bin edges, with every
+    quantity of the bin rule exact in FP64.
+
+    Sound speed 1024 m/s and fs = 2^25 Hz make the radial step c/fs = 2^-15 m;
+    the voxel spacing is one step (n odd: voxels at integer steps -(n-1)/2 ..
+    (n-1)/2 on each axis), t0 is an integer number of samples, and two
+    axis-aligned 8 x 8-step squares (4 x 4 points at odd integer steps) face the
+    grid from ``height`` steps along +z and along +x.  Every voxel straight
+    below (or beside) a point is an integer number of steps from it, so its
+    arrival lies exactly on the edge between two bins; the bin rule of Alg. 2
+    puts it in the upper one."""
+    c, fs = 1024.0, float(2 ** 25)
+    dr = c / fs
+    grid = Grid.centred(n, dr)
+    h = height * dr
+    half = 4 * dr
+    tr = Transducers(np.array([
+        planar([0.0, 0.0, h], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], half, half),
+        planar([h, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0], half, half),
+    ]))
+    coef = np.random.default_rng(12).random((1, grid.N))
+    p = _finish(f"exact_tie_{n}c", tr, grid, fs, L, coef, 13, quad=(4, 4), c=c)
+    p.meta["tie_step"] = dr
     return p
 
 

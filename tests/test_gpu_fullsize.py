@@ -3,8 +3,15 @@ checked against the FP64 oracle on sampled outputs it can compute one by one:
 the signals of a few transducers over every voxel, and the adjoint at a few
 thousand voxels over every transducer.  Dot tests use every output.
 
+Samples: the 128^3 x 256-cylinder workload on transducers k = 0 (mod 8) and
+voxels i = 0 (mod 257); the 256^3 x 512-planar workload on k = 0 (mod 32) and
+i = 0 (mod 4099); the batched workload on every transducer of every volume
+(its coefficients vanish outside balls, which the oracle skips) and 3000
+voxels.
+
 Tolerances: FP32 1e-5 relative L2 per sampled output set (and per volume for
-the batched workload).  FP64 2e-9: at full size the oracle and the FP64 kernels
+the batched workload), and per row (one transducer's signal of one volume,
+one volume's adjoint sample) max |gpu - oracle| <= ROW_TAU_FULL * max |oracle|.  FP64 2e-9: at full size the oracle and the FP64 kernels
 are two independent FP64 evaluations of the closed forms, each carrying ~1e-12
 relative rounding per bin in the cylinder (differences of nearly equal
 elliptic integrals), and the zero-mean system kernel amplifies relative errors
@@ -21,7 +28,7 @@ import torch
 
 import oracle as O
 import pat_inputs as P
-from conftest import rel_l2
+from conftest import ROW_TAU_FULL, rel_l2, row_ratio
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -62,17 +69,31 @@ def gpu_full(name, prec):
     return p, out
 
 
+def samples(name, p):
+    """Sampled transducers and voxels of each workload."""
+    if name == "cyl256_128c":
+        return np.arange(0, p.K, 8), np.arange(0, p.N, 257, dtype=np.int64)
+    if name == "planar512_256c":
+        return np.arange(0, p.K, 32), np.arange(0, p.N, 4099, dtype=np.int64)
+    return np.arange(p.K), np.linspace(0, p.N - 1, 3000).astype(np.int64)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("name,ks", [("cyl256_128c", [0, 131]), ("planar512_256c", [0, 300]), ("batch8_planar256_128c", [0, 77])])
-def test_fullsize_sampled_parity(gpu, name, ks, prec):
+@pytest.mark.parametrize("name", ["cyl256_128c", "planar512_256c", "batch8_planar256_128c"])
+def test_fullsize_sampled_parity(gpu, name, prec):
     p, (s, z) = gpu_full(name, prec)
-    vs = np.linspace(0, p.N - 1, 3000).astype(np.int64)
+    ks, vs = samples(name, p)
     s_ref, z_ref = oracle_samples(name, ks, vs)
+    worst_s = worst_z = 0.0
     for b in range(p.coef.shape[0]):
         es = rel_l2(s[b, ks], s_ref[b])
         ez = rel_l2(z[b, vs], z_ref[b])
-        print(f"[{name} {prec}] volume {b}: forward {es:.3e} adjoint {ez:.3e}", flush=True)
+        rs, rz = row_ratio(s[b, ks], s_ref[b]), row_ratio(z[b, vs], z_ref[b])
+        worst_s, worst_z = max(worst_s, rs), max(worst_z, rz)
+        print(f"[{name} {prec}] volume {b}: forward {es:.3e} (worst row {rs:.3e}) adjoint {ez:.3e} "
+              f"(max {rz:.3e} of the largest)", flush=True)
         assert es < TOL[prec] and ez < TOL[prec]
+    assert worst_s <= ROW_TAU_FULL[prec] and worst_z <= ROW_TAU_FULL[prec]
     # dot test over every output, reductions in FP64
     lhs, rhs = float(np.sum(s * p.y)), float(np.sum(z * p.coef))
     gap = abs(lhs - rhs) / (np.linalg.norm(s) * np.linalg.norm(p.y))

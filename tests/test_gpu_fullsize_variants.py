@@ -10,7 +10,7 @@ import torch
 
 import oracle as O
 import pat_inputs as P
-from conftest import rel_l2
+from conftest import ROW_TAU_FULL, rel_l2, row_ratio
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -41,5 +41,7 @@ def test_variant_at_full_size(gpu, mode, U, step):
     z = z[:, torch.tensor(vs, device=gpu)].double().cpu().numpy()
     op.close()
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
-    print(f"  forward {es:.3e}  adjoint {ez:.3e}", flush=True)
+    rs, rz = row_ratio(s, s_ref), row_ratio(z, z_ref)
+    print(f"  forward {es:.3e} (worst row {rs:.3e})  adjoint {ez:.3e} (worst row {rz:.3e})", flush=True)
     assert es < 1e-5 and ez < 1e-5
+    assert rs <= ROW_TAU_FULL["fp32"] and rz <= ROW_TAU_FULL["fp32"]

@@ -14,7 +14,7 @@ import torch
 
 import oracle as O
 import pat_inputs as P
-from conftest import rel_l2
+from conftest import ROW_TAU, rel_l2, row_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +50,8 @@ def test_multi_pass_windows(gpu, shape, B, passes, prec):
     z = op.adjoint(torch.tensor(p.y, dtype=DT[prec], device=gpu)).double().cpu().numpy()
     op.close()
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
-    print(f"  forward {es:.3e} adjoint {ez:.3e}", flush=True)
+    rs, rz = row_ratio(s, s_ref), row_ratio(z, z_ref)
+    print(f"  forward {es:.3e} (worst row {rs:.3e}) adjoint {ez:.3e} (worst row {rz:.3e})", flush=True)
     assert np.linalg.norm(s_ref) > 0
     assert es < TOL[prec] and ez < TOL[prec]
+    assert rs <= ROW_TAU[prec] and rz <= ROW_TAU[prec]

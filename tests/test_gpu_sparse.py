@@ -12,7 +12,7 @@ import torch
 
 import oracle as O
 import pat_inputs as P
-from conftest import rel_l2
+from conftest import ROW_TAU, ROW_TAU_FULL, rel_l2, row_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,10 @@ def test_sparse_forward_matches_full_and_oracle(gpu, prec, mode):
     ks = np.arange(0, p.K, 37, dtype=np.int32)
     s_ref = O.forward(p, ksub=ks, mode=OMODE[mode])
     e_self, e_ref = rel_l2(s_sp, s_full), rel_l2(s_sp[:, ks], s_ref)
-    print(f"  sparse vs full {e_self:.3e}   sparse vs oracle {e_ref:.3e}", flush=True)
+    r_ref = row_ratio(s_sp[:, ks], s_ref)
+    print(f"  sparse vs full {e_self:.3e}   sparse vs oracle {e_ref:.3e} (worst row {r_ref:.3e})", flush=True)
     assert e_self < SELF[prec] and e_ref < TOL[prec]
+    assert r_ref <= ROW_TAU_FULL[prec]
 
 
 def test_sparse_forward_full_lib_scan(gpu):
@@ -62,9 +64,10 @@ def test_sparse_forward_full_lib_scan(gpu):
     got = s[:, torch.tensor(ks, device=gpu).long()].double().cpu().numpy()
     op.close()
     ref = O.forward(p, ksub=ks)
-    e = rel_l2(got, ref)
-    print(f"  sampled rel L2 vs oracle {e:.3e}", flush=True)
+    e, r = rel_l2(got, ref), row_ratio(got, ref)
+    print(f"  sampled rel L2 vs oracle {e:.3e} (worst row {r:.3e})", flush=True)
     assert np.linalg.norm(ref) > 0 and e < TOL["fp32"]
+    assert r <= ROW_TAU_FULL["fp32"]
 
 
 @pytest.mark.parametrize("fill", ["dense", "empty", "batch"])

@@ -15,7 +15,7 @@ import torch
 
 import oracle as O
 import pat_inputs as P
-from conftest import rel_l2
+from conftest import ROW_TAU, rel_l2, row_ratio
 
 pytestmark = pytest.mark.gpu
 
@@ -71,8 +71,11 @@ def test_variant_parity(gpu, case, prec):
     z_ref = O.adjoint(p, mode=OMODE[mode])
     s, z, evals = run_gpu(p, mode, prec, step)
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
-    print(f"  forward rel L2 {es:.3e}  adjoint rel L2 {ez:.3e}  area evaluations {evals:.0f}", flush=True)
+    rs, rz = row_ratio(s, s_ref), row_ratio(z, z_ref)
+    print(f"  forward rel L2 {es:.3e} (worst row {rs:.3e})  adjoint rel L2 {ez:.3e} (worst row {rz:.3e})  "
+          f"area evaluations {evals:.0f}", flush=True)
     assert es < TOL[prec] and ez < TOL[prec]
+    assert rs <= ROW_TAU[prec] and rz <= ROW_TAU[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -86,8 +89,11 @@ def test_lut_reaches_the_nu_above_one_branch(gpu, prec):
     s, z, _ = run_gpu(p, "lut", prec, 1)
     es, ez = rel_l2(s, s_ref), rel_l2(z, z_ref)
     ex = rel_l2(s, O.forward(p))
-    print(f"lut {prec}: forward {es:.3e} adjoint {ez:.3e}; method error vs exact {ex:.3e}", flush=True)
+    rs, rz = row_ratio(s, s_ref), row_ratio(z, z_ref)
+    print(f"lut {prec}: forward {es:.3e} adjoint {ez:.3e} (worst rows {rs:.3e}, {rz:.3e}); "
+          f"method error vs exact {ex:.3e}", flush=True)
     assert es < TOL[prec] and ez < TOL[prec]
+    assert rs <= ROW_TAU[prec] and rz <= ROW_TAU[prec]
     assert ex < 1e-3
 
 

@@ -526,3 +526,37 @@ def test_surface_converges_to_point_with_many_points():
         errs.append(rel_l2(O.forward(p, mode=O.MODE_POINT, kernel=(h, nf)), fsurf))
     assert errs[-1] < errs[0] / 10
     assert errs[-1] < 0.05
+
+
+def test_point_bin_rule_on_exact_ties():
+    """Alg. 2's bin rule l = floor((r/c - t0) U F_s) + 1 on distances that lie
+    exactly on bin edges (reading 1: half-open bins, a distance on an edge goes
+    to the upper bin), against brute force in exact integer arithmetic: in the
+    exact-tie workload every distance is sqrt of an integer number of squared
+    radial steps, so floor(r / dr) = isqrt(r^2 / dr^2) with no rounding."""
+    p = P.exact_tie_case()
+    dr = p.meta["tie_step"]
+    ufs = p.U * p.fs
+    r0 = int(round(p.t0 * ufs))
+    assert r0 == p.t0 * ufs
+    n = p.grid.n[0]
+    h, nf = O.kernel_of(p)
+    ties = 0
+    for k in range(p.K):
+        f_or, Mlo = O.fcoef(p, k, mode=O.MODE_POINT, kernel=(h, nf))
+        pts, dA = O.quad_points(p.tr.packed[k], *p.quad_n)
+        ip = np.rint(pts / dr).astype(np.int64)
+        assert np.array_equal(ip * dr, pts)               # points on the integer lattice of dr
+        f = np.zeros_like(f_or)
+        for i in range(p.N):
+            vox = np.array([i % n, (i // n) % n, i // (n * n)]) - (n - 1) // 2
+            for q in ip:
+                r2 = int(np.sum((q - vox) ** 2))
+                s = math.isqrt(r2)
+                ties += s * s == r2
+                m = s - r0 + 1                              # floor(r/dr - r0) + 1
+                f[0, m - Mlo] += p.coef[0, i] * dA / (math.sqrt(r2) * dr)
+        f *= ufs
+        assert rel_l2(f_or, f) < 1e-14
+        assert np.max(np.abs(f_or - f)) <= 1e-13 * np.max(np.abs(f))
+    assert ties >= 2 * 16 * n
