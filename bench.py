@@ -267,6 +267,70 @@ def run_lib(torch, dev, log):
     return rows
 
 
+def run_pgd(torch, dev, log, ckdir):
+    """Config 4's reconstruction at its stated size: 192^3 voxels (0.1 mm), 384
+    cylinders (24 elements x 16 rotations), fs 50 MHz, L = 2048, FP32 I/O; y =
+    A c_true + 1 % Gaussian noise (relative to max |A c_true|, seed 6) for a
+    24-polyline phantom (seed 5); step 0.9 / lambda with lambda the largest
+    eigenvalue of A^T A from 20 power iterations (seed 7); c = 0 and 50
+    projected-gradient iterations c <- max(0, c - step A^T (A c - y)), a
+    checkpoint file every 10 iterations; then a resume from the file of
+    iteration 40 through iteration 50, compared with the uninterrupted run."""
+    import numpy as np
+    import pat_inputs as P
+    from paper_2609_29253_amd.operator import (PatOperator, load_checkpoint, power_iteration,
+                                               projected_gradient)
+    p = P.pgd_cyl384_192c()
+    iters = int(p.meta["iterations"])
+    log(f"[bench] pgd: {p.name} N={p.N} K={p.K} L={p.L}, {iters} iterations, checkpoints in {ckdir}")
+    op = PatOperator.from_problem(p, mode="closed", precision="fp32")
+    truth = torch.tensor(p.coef, dtype=torch.float32, device=dev)
+    clean = op.forward(truth)
+    g = torch.Generator().manual_seed(p.meta["noise_seed"])
+    noise = torch.randn(clean.shape, generator=g, dtype=torch.float64).to(dev, torch.float32)
+    y = clean + p.meta["noise_level"] * clean.abs().max() * noise
+    tn = float(torch.linalg.vector_norm(truth))
+    t = time.perf_counter()
+    lam = power_iteration(op, iters=20, seed=p.meta["power_seed"])
+    t_pow = time.perf_counter() - t
+    step = 0.9 / lam
+    log(f"[bench] pgd: lambda_max(A^T A) = {lam:.6e} from 20 power iterations in {t_pow:.1f}s, step {step:.6e}")
+    marks = {"t": time.perf_counter()}
+    times, errs = [], {}
+
+    def cb(it, c, losses):
+        now = time.perf_counter()
+        times.append(now - marks["t"])
+        marks["t"] = now
+        if it % 10 == 0 or it == 1:
+            errs[it] = float(torch.linalg.vector_norm(c - truth)) / tn
+        log(f"[bench] pgd: iteration {it}: loss {losses[-1]:.6e}, {times[-1] * 1e3:.0f} ms"
+            + (f", |c - c_true|/|c_true| {errs[it]:.4f}" if it in errs else ""))
+
+    ck = os.path.join(ckdir, "pgd_{it}.pt")
+    c, losses = projected_gradient(op, y, iters, step, callback=cb, checkpoint=ck, every=10)
+    monotone = all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:]))
+    err = float(torch.linalg.vector_norm(c - truth)) / tn
+    st = load_checkpoint(ck.replace("{it}", str(iters - 10)))
+    t = time.perf_counter()
+    c_res, l_res = projected_gradient(op, y, iters, step, state=st)
+    t_res = time.perf_counter() - t
+    resume_rel = float(torch.linalg.vector_norm(c_res - c) / torch.linalg.vector_norm(c))
+    loss_rel = max(abs(a - b) / abs(b) for a, b in zip(l_res[iters - 10:], losses[iters - 10:]))
+    op.close()
+    it_ms = 1e3 * float(np.median(times))
+    row = {"workload": p.name, "voxels": p.N, "transducers": p.K, "samples": p.L, "iterations": iters,
+           "io_precision": "fp32", "lambda_max": lam, "step": step, "power_iteration_s": round(t_pow, 2),
+           "ms_per_iteration_median": round(it_ms, 1), "ms_per_iteration_mean": round(1e3 * float(np.mean(times)), 1),
+           "pairs_per_s_A_plus_AT": float(p.N) * p.K / (it_ms * 1e-3),
+           "loss_first": losses[0], "loss_last": losses[-1], "loss_monotone": monotone,
+           "rel_err_to_truth_by_iteration": errs, "rel_err_to_truth": err,
+           "resume_from_iteration": iters - 10, "resume_s": round(t_res, 2),
+           "resume_rel_diff_final_iterate": resume_rel, "resume_max_rel_diff_losses": loss_rel}
+    log(f"[bench] pgd: {row}")
+    return row
+
+
 def run_cpu_table(torch, dev, log):
     """Per configuration: the closed form's A + A^T rate on the GPU (FP32 I/O) and
     the oracle's on the host, on all its threads and on one, each over a bounded
@@ -338,6 +402,11 @@ def main():
     ap.add_argument("--lib", action="store_true",
                     help="only the LIB-scale rows (sparse forward at U = 61, dense A + A^T at U = 11 on a "
                          "sub-scan), printed as one JSON object instead of the benchmark line")
+    ap.add_argument("--pgd", action="store_true",
+                    help="only config 4's projected-gradient reconstruction at its stated size (192^3 voxels, "
+                         "384 cylinders, 50 iterations, checkpoints every 10, a resume from iteration 40), "
+                         "printed as one JSON object instead of the benchmark line")
+    ap.add_argument("--pgd-dir", default=None, help="folder for the --pgd checkpoints (default: a temporary one)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only the per-configuration GPU and oracle rates (planar64_32c, cyl256_128c, planar512_256c, batch8_planar256_128c), printed as one "
                          "JSON object instead of the benchmark line")
@@ -354,6 +423,13 @@ def main():
     if args.lib:
         dev = torch.device("cuda", 0)
         print(json.dumps({"lib_rows": run_lib(torch, dev, log)}), flush=True)
+        return
+    if args.pgd:
+        import tempfile
+        dev = torch.device("cuda", 0)
+        ckdir = args.pgd_dir or tempfile.mkdtemp(prefix="pgd_")
+        os.makedirs(ckdir, exist_ok=True)
+        print(json.dumps({"pgd": run_pgd(torch, dev, log, ckdir)}), flush=True)
         return
     if args.cpu_table:
         dev = torch.device("cuda", 0)

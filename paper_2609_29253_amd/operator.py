@@ -184,10 +184,38 @@ def power_iteration(op: PatOperator, iters: int = 20, seed: int = 7) -> float:
     return lam
 
 
+def save_checkpoint(path: str, it: int, c: torch.Tensor, losses, step: float) -> None:
+    """Projected-gradient state after iteration ``it``: the iterate (on the
+    host, bit for bit), the loss history, the step size and torch's CPU random
+    state, written to a temporary file and renamed over ``path`` so that a
+    crash never leaves a partial checkpoint."""
+    import os
+    tmp = f"{path}.tmp"
+    torch.save({"it": int(it), "c": c.detach().cpu().clone(), "losses": [float(v) for v in losses],
+                "step": float(step), "rng_cpu": torch.get_rng_state()}, tmp)
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str) -> dict:
+    """A checkpoint written by ``save_checkpoint`` (tensors and plain numbers
+    only: loaded with weights_only=True)."""
+    st = torch.load(path, map_location="cpu", weights_only=True)
+    torch.set_rng_state(st["rng_cpu"])
+    return st
+
+
 def projected_gradient(op: PatOperator, y: torch.Tensor, iters: int, step: float,
-                       c0: Optional[torch.Tensor] = None, callback=None, state: Optional[dict] = None):
-    """c <- max(0, c - step * A^T (A c - y)); returns (c, loss history).
-    ``state`` (from a checkpoint: {'it', 'c', 'losses'}) resumes exactly."""
+                       c0: Optional[torch.Tensor] = None, callback=None, state: Optional[dict] = None,
+                       checkpoint: Optional[str] = None, every: int = 10):
+    """c <- max(0, c - step * A^T (A c - y)); returns (c, loss history), where
+    losses[j] = 0.5 |A c_j - y|^2 of the iterate entering iteration j.
+    ``checkpoint``: a file written after every ``every`` iterations (and the
+    last) with ``save_checkpoint``; a "{it}" in the name is replaced by the
+    iteration count (one file per checkpoint), otherwise the file is rewritten.
+    ``state`` (a loaded checkpoint, or a dict {'it', 'c', 'losses'}) resumes
+    from that iteration with its iterate bit for bit; the operator's forward
+    sums its FP64 fine-bin terms in a run-dependent order, so later iterates
+    match an uninterrupted run to rounding only."""
     if state is not None:
         c = state["c"].to(op.device, op.dtype).clone()
         losses = list(state["losses"])
@@ -202,4 +230,6 @@ def projected_gradient(op: PatOperator, y: torch.Tensor, iters: int, step: float
         c = torch.clamp(c - step * op.adjoint(r), min=0.0)
         if callback is not None:
             callback(it + 1, c, losses)
+        if checkpoint is not None and ((it + 1) % every == 0 or it + 1 == iters):
+            save_checkpoint(checkpoint.replace("{it}", str(it + 1)), it + 1, c, losses, step)
     return c, losses

@@ -26,10 +26,12 @@ def rel_l2(a, b):
 # transducer's signal of one volume, or one volume's adjoint sample),
 # max |gpu - ref| <= ROW_TAU * max |ref| over that row.  The relative L2 bar
 # (1e-5 in FP32) averages over the whole output; this one catches an error
-# confined to one transducer or a few samples.  FP32 I/O: measured 1e-7 to
-# 4e-7 of the row maximum, bar 1e-6.  FP64: two independent FP64 evaluations
-# of the closed forms, amplified 20-300x by the zero-mean kernel (small
-# cases 1e-12 .. 1e-11, full size ~1e-9).
+# confined to one transducer or a few samples.  Measured on the MI355X: FP32
+# I/O up to 3.3e-7 of the row maximum on the small cases and 6.1e-7 at full
+# size (256^3 x 512 planar), bar 1e-6; FP64 (two independent FP64
+# evaluations of the closed forms, amplified 20-300x by the zero-mean
+# kernel) up to 5e-12 on the small cases and 2.2e-9 at full size (128^3 x 256
+# cylinders), bars 2e-11 and 5e-9.
 ROW_TAU = {"fp32": 1e-6, "fp64": 2e-11}
 ROW_TAU_FULL = {"fp32": 1e-6, "fp64": 5e-9}
 
