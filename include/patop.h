@@ -176,6 +176,21 @@ pat_status pat_forward_sparse(pat_ctx* ctx, const void* coef, void* signal, int3
 pat_status pat_adjoint(pat_ctx* ctx, const void* signal, void* coef, int32_t batch,
                        void* hip_stream);
 
+/* signal = A coef like pat_forward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the call allocates nothing and frees nothing.  Its only scratch,
+ * the FP64 fine-bin coefficients ([batch][K][fine bins kept] doubles), lives
+ * in a static device array of 64 MiB per GPU that the library holds until the
+ * process ends, cleared by a kernel at every call (the context's own
+ * workspace is not used).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams, other contexts, other threads) race and
+ * must be serialised by the caller.  Same arguments, layouts and result as
+ * pat_forward; PAT_E_UNSUPPORTED when batch * K * (fine bins kept) * 8 bytes
+ * exceeds 64 MiB (pat_query(2) gives the fine bins kept), PAT_E_DEVICE if the
+ * array's address could not be looked up when the context was created. */
+pat_status pat_forward_noalloc(pat_ctx* ctx, const void* coef, void* signal, int32_t batch,
+                               void* hip_stream);
+
 /* Host-only, FP64: discrete system kernel h[n] of Eq. def_bh for
  * g(t) = -1/2 c t phi(c|t|) (Prop. 1) with phi = cone or Wendland
  * (1 - r/kappa)^2_+, h = e * g (Eq. def_h), on the fine grid of step

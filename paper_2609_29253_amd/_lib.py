@@ -22,7 +22,8 @@ PAT_FP32, PAT_FP64 = 0, 1
 PAT_PHI_CONE, PAT_PHI_WENDLAND2 = 0, 1
 PAT_EIR_GAUSS_COS, PAT_EIR_SAMPLED = 0, 1
 
-EXPORTED = ["pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_adjoint",
+EXPORTED = ["pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_forward_noalloc",
+            "pat_adjoint",
             "pat_build_kernel", "pat_check_geometry", "pat_query", "pat_probe_peak", "pat_status_string",
             "pat_last_error", "pat_destroy"]
 
@@ -84,6 +85,7 @@ def lib():
     L.pat_set_geometry.argtypes = [c.c_void_p, P(Transducer), c.c_int32, P(Grid), P(Kernel), P(Params)]
     L.pat_forward.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p, c.c_int32, c.c_void_p]
     L.pat_forward_sparse.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p, c.c_int32, c.c_void_p]
+    L.pat_forward_noalloc.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p, c.c_int32, c.c_void_p]
     L.pat_adjoint.argtypes = [c.c_void_p, c.c_void_p, c.c_void_p, c.c_int32, c.c_void_p]
     L.pat_build_kernel.argtypes = [c.c_int32, c.c_double, P(Eir), c.c_double, c.c_double, c.c_int32,
                                    P(c.c_double), c.c_int64, P(c.c_int64), P(c.c_int64)]
@@ -96,7 +98,8 @@ def lib():
     L.pat_last_error.restype = c.c_char_p
     L.pat_destroy.argtypes = [c.c_void_p]
     L.pat_destroy.restype = None
-    for name in ("pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_adjoint",
+    for name in ("pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_forward_noalloc",
+                 "pat_adjoint",
                  "pat_build_kernel", "pat_check_geometry", "pat_query", "pat_probe_peak"):
         getattr(L, name).restype = c.c_int32
     _lib = L

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,54 @@
 #include "patop.h"
 
 using namespace patop;
+
+// Scratch of pat_forward_noalloc: the FP64 fine-bin coefficients f of one
+// forward ([batch][K][Mcount] doubles), in a file-scope device array instead
+// of the context's workspace, for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// uses the array's name as an address: pat_create looks up each device's
+// address once (that device current) and the entry point passes that pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchTable {
+    std::mutex mu;
+    bool done[kMaxDevices] = {};
+    hipError_t err[kMaxDevices] = {};
+    void* ptr[kMaxDevices] = {};
+};
+
+ScratchTable& scratch_table()
+{
+    static ScratchTable t;
+    return t;
+}
+
+// device address of `scratch` on `device`, looked up at its first request with
+// that device current (the caller has made it current); the status of the
+// lookup is kept with it
+hipError_t scratch_lookup(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    ScratchTable& t = scratch_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (!t.done[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        t.err[device] = e;
+        t.ptr[device] = e == hipSuccess ? p : nullptr;
+        t.done[device] = true;
+    }
+    *out = t.ptr[device];
+    return t.err[device];
+}
+
+}  // namespace
 
 struct pat_ctx {
     int device = 0;
@@ -194,6 +243,13 @@ pat_status pat_create(pat_ctx** out, int32_t device)
     pat_ctx* c = new (std::nothrow) pat_ctx();
     if (!c) return PAT_E_OOM;
     c->device = device;
+    {
+        // the no-allocation forward's scratch address on this device (kept
+        // with its status; pat_forward_noalloc reports a failed lookup)
+        DevGuard guard(device);
+        void* p = nullptr;
+        if (guard.ok) (void)scratch_lookup(device, &p);
+    }
     *out = c;
     return PAT_OK;
 }
@@ -525,6 +581,33 @@ pat_status pat_forward_sparse(pat_ctx* c, const void* coef, void* signal, int32_
 pat_status pat_adjoint(pat_ctx* c, const void* signal, void* coef, int32_t batch, void* stream)
 {
     return run(c, signal, coef, batch, stream, Op::adjoint);
+}
+
+pat_status pat_forward_noalloc(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
+{
+    if (!c) return PAT_E_ARG;
+    if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
+    if (!coef || !signal || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
+    const double need = (double)batch * c->K * (double)c->plan.base.Mcount * sizeof(double);
+    if (need > (double)kScratchBytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "forward_noalloc needs %.0f bytes of scratch (batch x K x fine bins x 8), above its static "
+                 "%zu bytes; use pat_forward",
+                 need, kScratchBytes);
+        return fail(c, PAT_E_UNSUPPORTED, buf);
+    }
+    DevGuard guard(c->device);
+    if (!guard.ok) return fail(c, PAT_E_DEVICE, "hipSetDevice failed");
+    void* p = nullptr;
+    hipError_t e = scratch_lookup(c->device, &p);
+    if (e != hipSuccess || !p)
+        return fail(c, PAT_E_DEVICE, std::string("scratch address lookup failed: ") + hipGetErrorString(e));
+    LaunchPlan plan = c->plan;   // the context's tables; f in the static scratch
+    plan.f = static_cast<double*>(p);
+    e = launch_forward(plan, coef, signal, batch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(c, PAT_E_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return PAT_OK;
 }
 
 pat_status pat_query(const pat_ctx* c, int32_t what, double* out)
