@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpatop.so")
-SOURCES = ["host.hip", "kernels.hip", "kernel_builder.cpp", "probe.hip"]
+SOURCES = ["host.hip", "kernels.hip", "kernel_builder.cpp", "geometry.cpp", "probe.hip"]
 ARCH = os.environ.get("PATOP_ARCH", "gfx950")
 
 FLAGS = [
