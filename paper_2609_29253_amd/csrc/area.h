@@ -55,9 +55,37 @@ namespace patop {
 // small numeric helpers
 // ---------------------------------------------------------------------------
 
+// Seeds of the FP64 reciprocal and reciprocal square root.  NW = 1 (one
+// correction step, the FP32-I/O cylinder kernels): the FP32 instructions
+// v_rcp_f32 / v_rsq_f32 (1 ulp, 2^-23), which on gfx950 cost, with their two
+// conversions, about half of v_rcp_f64 / v_rsq_f64; one Newton step then leaves
+// 2^-46 (rcp) and 1.5 x 2^-46 (rsq) relative error.  Their arguments must lie
+// in the FP32 normal range (or be <= 0 where the result is not used).  NW >= 2:
+// the FP64 instructions (~2^-24), two steps to full precision.
+template <int NW>
+__device__ __forceinline__ double rcp_seed(double x)
+{
+    if (NW == 1) return (double)__builtin_amdgcn_rcpf((float)x);
+    return __builtin_amdgcn_rcp(x);
+}
+template <int NW>
+__device__ __forceinline__ double rsq_seed(double x)
+{
+    if (NW == 1) return (double)__builtin_amdgcn_rsqf((float)x);
+    return __builtin_amdgcn_rsq(x);
+}
+
+// the offset that keeps square-root arguments positive (and, for NW = 1, in
+// the FP32 normal range of the seeds); below any length or cosine that enters
+// a sum here
+template <int NW> struct Tiny { static constexpr double value = 1e-300; };
+template <> struct Tiny<1> { static constexpr double value = 1e-30; };
+
+// 1/x with one Newton step
+template <int NW = 2>
 __device__ __forceinline__ double rcp64(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
+    double r = rcp_seed<NW>(x);
     return fma(r, fma(-x, r, 1.0), r);
 }
 
@@ -91,7 +119,7 @@ __device__ __forceinline__ double rcp64_full(double x)
 template <int NEWTON = 2>
 __device__ __forceinline__ double rsq64(double x)
 {
-    double r = __builtin_amdgcn_rsq(x);
+    double r = rsq_seed<NEWTON>(x);
 #pragma unroll
     for (int i = 0; i < NEWTON; ++i) {
         double h = 0.5 * x * r;
@@ -107,7 +135,7 @@ __device__ __forceinline__ double rsq64(double x)
 template <int NEWTON = 2>
 __device__ __forceinline__ double sqrt64_pos(double x)
 {
-    const double y = __builtin_amdgcn_rsq(x);
+    const double y = rsq_seed<NEWTON>(x);
     double g = x * y, h = 0.5 * y;
     if (NEWTON >= 2) {
         const double r = fma(-g, h, 0.5);
@@ -117,12 +145,13 @@ __device__ __forceinline__ double sqrt64_pos(double x)
     return fma(fma(-g, g, x), h, g);
 }
 
-// sqrt(max(x, 1e-300)): branch free; returns 1e-150 instead of 0 for x <= 0,
-// which is below any length or cosine that enters a sum here
+// sqrt(max(x, tiny)): branch free; returns sqrt(tiny) (1e-150, or 1e-15 with the
+// FP32 seeds) instead of 0 for x <= 0, below any length or cosine that enters a
+// sum here
 template <int NEWTON = 2>
 __device__ __forceinline__ double sqrt64(double x)
 {
-    return sqrt64_pos<NEWTON>(fmax(x, 1e-300));
+    return sqrt64_pos<NEWTON>(fmax(x, Tiny<NEWTON>::value));
 }
 
 // FP32 square root as the one v_sqrt_f32 (1 ulp); the IEEE-rounded sqrtf the
@@ -501,13 +530,14 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // fixed initial deviation, and the factors 2^n that the scaling leaves on
 // R_F and on the R_D series are applied once at the end.  With c^2, D^2 <= 1
 // = z, z stays the largest argument, so A_D = (x + y + 3z)/5 >= A_F = (x + y
-// + z)/3 and the test needs A_F only.  x and y start at c^2 + 1e-300 and D^2 +
-// 1e-300 (the same values unless they are below 1e-284), so every square root
-// in the loop has a positive argument.
+// + z)/3 and the test needs A_F only.  x and y start at c^2 + tiny and D^2 +
+// tiny (tiny = 1e-300, or 1e-30 for the FP32 seeds of NW = 1, which changes
+// R_F and R_D by ~1e-15 relative at most), so every square root in the loop
+// has a positive argument.
 template <int NW, bool TABLE = false>
 __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, double nu, double* f_out = nullptr)
 {
-    double x = fma(c, c, 1e-300), y = fma(dl, dl, 1e-300), z = 1.0;
+    double x = fma(c, c, Tiny<NW>::value), y = fma(dl, dl, Tiny<NW>::value), z = 1.0;
     double sx = fabs(c), sy = dl, sz = 1.0;
     double AF = (x + y + z) * (1.0 / 3.0);
     double AD = (x + y + 3.0 * z) * 0.2;
@@ -520,7 +550,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
         // the first step, with z = sqrt(z) = 1
         const double lam = fma(sx, sy, sx + sy);
         z += lam;
-        sumD = rcp64(z);
+        sumD = rcp64<NW>(z);
         x += lam;
         y += lam;
         AF += lam;
@@ -531,7 +561,7 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
 #pragma unroll 1
         for (int it = 1; it < itmax && thr >= AF; ++it) {
             double lam = fma(sx, sy, fma(sx, sz, sy * sz));
-            sumD = fma(p2, rcp64(sz * (z + lam)), sumD);
+            sumD = fma(p2, rcp64<NW>(sz * (z + lam)), sumD);
             x += lam;
             y += lam;
             z += lam;
@@ -710,7 +740,7 @@ __device__ __forceinline__ void cy_edge(const CyQuad& q, const CyPair& P, double
     }
     const double sbda = E.sb * E.da, sbsa = E.sb * E.sa, dd = E.db * E.da, nss = nu * sbsa;
     double den = fma(E.cb, E.cb, sbda * sbda);   // 1 - nu sin^2 sin^2
-    double idn = rcp64(den);
+    double idn = rcp64<NW>(den);
     double ss = fma(sbda, E.ca, -E.sa * (E.cb * E.db)) * idn;
     double cs = fma(E.cb, E.ca, sbsa * dd) * idn;
     double ds = fma(nss, E.cb * E.ca, dd) * idn;
