@@ -193,17 +193,28 @@ __device__ __forceinline__ T sdiv(T n, T d)
     return d > T(0) ? n * rcp_t(d) : T(0);
 }
 
-// atan(x) - x for x >= 0 without cancellation: halving
+// atan(x) - x and atan(x) for x >= 0, the first without cancellation: halving
 //   atan x - x = 2 (atan y - y) - x^3 / (1 + sqrt(1 + x^2))^2,  y = x / (1 + sqrt(1 + x^2)),
-// then the Taylor series of atan y - y, through y^13; its relative truncation
-// error is ~0.2 y^12: below 1.2e-8 (FP32) from y < 0.25, below 2e-13 (the
-// FP64 series runs to y^23) from y < 0.1.
+// (atan x = 2 atan y) then the Taylor series of atan y - y, through y^13; its
+// relative truncation error is ~0.2 y^12: below 1.2e-8 (FP32) from y < 0.25,
+// below 2e-13 (the FP64 series runs to y^23) from y < 0.1.  Above 4 the
+// library's atan gives both (there the difference has no cancellation).
+template <class T>
+struct AtanPair {
+    T mx;   // atan x - x
+    T a;    // atan x
+};
+
 template <class T> struct AtanMx;
 
 template <> struct AtanMx<float> {
-    static __device__ __forceinline__ float eval(float x)
+    static __device__ __forceinline__ AtanPair<float> eval(float x)
     {
-        if (x > 4.0f) return atanf(x) - x;
+        if (x > 4.0f) {
+            const float a = atanf(x);
+            return {a - x, a};
+        }
+        const float x0 = x;
         float acc = 0.0f, scale = 1.0f;
         for (int i = 0; i < 4 && x >= 0.25f; ++i) {
             float q = 1.0f + __builtin_amdgcn_sqrtf(fmaf(x, x, 1.0f));
@@ -215,14 +226,21 @@ template <> struct AtanMx<float> {
         float y = x * x;
         float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, -1.0f / 13, 1.0f / 11), -1.0f / 9), 1.0f / 7), -1.0f / 5),
                        1.0f / 3);
-        return fmaf(-scale * x * y, p, acc);
+        const float t = -scale * x * y * p;   // 2^k (atan y_k - y_k)
+        // after halvings the reduced argument carries their rounding (~10 ulp
+        // after four), harmless in atan x - x but not in the angle itself,
+        // which then comes from the library
+        return {acc + t, scale > 1.0f ? atanf(x0) : x + t};
     }
 };
 
 template <> struct AtanMx<double> {
-    static __device__ __forceinline__ double eval(double x)
+    static __device__ __forceinline__ AtanPair<double> eval(double x)
     {
-        if (x > 4.0) return atan(x) - x;
+        if (x > 4.0) {
+            const double a = atan(x);
+            return {a - x, a};
+        }
         double acc = 0.0, scale = 1.0;
         for (int i = 0; i < 4 && x >= 0.1; ++i) {
             double q = 1.0 + sqrt64(fma(x, x, 1.0));
@@ -243,20 +261,10 @@ template <> struct AtanMx<double> {
         p = fma(y, p, 1.0 / 7);
         p = fma(y, p, -1.0 / 5);
         p = fma(y, p, 1.0 / 3);
-        return fma(-scale * x * y, p, acc);
+        const double t = -scale * x * y * p;
+        return {acc + t, fma(scale, x, t)};
     }
 };
-
-// correction C(p; s0, s1) of the integral of acos(p/sqrt s) over [s0, s1]
-template <class T>
-__device__ __forceinline__ T corr(T p, T s0, T dl, T w0, T w1)
-{
-    T ws = w0 + w1;
-    if (!(p > T(0)) || !(dl > T(0)) || !(ws > T(0))) return T(0);
-    T dw = dl * rcp_t(ws);
-    T x = p * dw * rcp_t(fma(p, p, w0 * w1));
-    return fma(s0, AtanMx<T>::eval(x), -x * w0 * dw);
-}
 
 // ---------------------------------------------------------------------------
 // planar quadrant
@@ -309,97 +317,133 @@ __device__ __forceinline__ T pl_qedge(const PlQuad<T>& q, int X, int m)
 
 enum { KEDGE = 0, KAC = 1, KAD = 2, KBC = 3, KBD = 4 };
 
+// One arc end point moving along its line (at distance p from the origin, leg
+// w along the line) between in-plane squared radii s0 and s1 = s0 + dl:
+//   dw = w1 - w0 = dl / (w0 + w1),   x = tan(angle swept) = p dw / (p^2 + w0 w1),
+// and, with theta(s) = acos(p / sqrt s) for the end point's angle,
+//   int_{s0}^{s1} theta ds = dl theta(s1) + C,   C = s0 (atan x - x) - x w0 dw
+// (C for asin(p / sqrt s) with the opposite sign), while the angle swept is
+// atan x.  p = 0 or dl = 0 give C = 0 and no angle.
+template <class T>
+struct PlSwept {
+    T C, A;
+};
+
+template <class T>
+__device__ __forceinline__ PlSwept<T> pl_swept(T p, T s0, T dl, T w0, T w1)
+{
+    const T tiny = T(1e-30);
+    const T dw = dl * rcp_t(fmax(w0 + w1, tiny));
+    const T x = p * dw * rcp_t(fmax(fma(p, p, w0 * w1), tiny));
+    const AtanPair<T> at = AtanMx<T>::eval(x);
+    return {fma(s0, at.mx, -x * w0 * dw), at.a};
+}
+
+// Theta(s) at an edge inside the quadrant's range, for a pass that starts
+// after the quadrant's first bin: the angle between the arc's end points from
+// one atan2 of the chord between them (cancellation free: every difference of
+// nearby squares comes from the corner offsets Q[X] = s - s_X)
+template <class T>
+__device__ __forceinline__ double pl_arc_angle(const PlQuad<T>& q, bool hiS, bool loA, const T Q[4], T wh, T wl)
+{
+    const T xh = hiS ? wh : q.a, yh = hiS ? q.d : wh;
+    const T xl = loA ? q.b : wl, yl = loA ? wl : q.c;
+    T chx, chy;
+    if (!hiS && !loA) {
+        chx = -sdiv(Q[0], q.a + wl);
+        chy = sdiv(Q[0], wh + q.c);
+    } else if (!hiS) {
+        chx = q.a - q.b;
+        chy = sdiv(q.gu, wh + wl);
+    } else if (!loA) {
+        chx = -sdiv(q.gv, wh + wl);
+        chy = q.d - q.c;
+    } else {
+        chx = sdiv(Q[3], wh + q.b);
+        chy = -sdiv(Q[3], q.d + wl);
+    }
+    return atan2((double)fma(xl, chy, -yl * chx), (double)fma(xl, xh, yl * yh));
+}
+
 // Walk the bins [max(mfirst, wlo), min(mlast, whi)] of a planar quadrant; sink(m, area)
-// receives the area in dr^2 units.
+// receives the area in dr^2 units.  A bin is cut into pieces at the corners
+// a^2 + d^2 (the upper end point moves from the line u = a to v = d), b^2 + c^2
+// (the lower one from v = c to u = b) and b^2 + d^2 (the end), at most three;
+// each piece adds dl Theta(s1) + (corrections of both end points) to twice the
+// bin's area, and Theta is carried from piece to piece by the angles the end
+// points sweep (in FP64), so no piece evaluates an inverse trigonometric
+// function of its own.  The piece's kind of end and its squared-radius offsets
+// are chosen by selects, not branches.
 template <class T, class Sink>
 __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T wgt, Sink& sink)
 {
     const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
     if (mb > me) return;
-    T Q0[4], s0;
+    // state at the start of the piece: offsets Q0[X] = s0 - s_X (X = AD, BC, BD),
+    // s0, the kind of start, which lines the end points are on, their legs, Theta
+    T Q01, Q02, Q03, s0, wh0, wl0;
     int kind0;
     bool hiS, loA;
+    double th;
     if (mb == q.mfirst) {
-        Q0[0] = T(0); Q0[1] = -q.gv; Q0[2] = -q.gu; Q0[3] = -(q.gu + q.gv);
+        Q01 = -q.gv; Q02 = -q.gu; Q03 = -(q.gu + q.gv);
         s0 = q.s[0];
         kind0 = KAC;
         hiS = false;
         loA = false;
+        wh0 = q.c;
+        wl0 = q.a;
+        // Theta just above the nearest corner (a, c): 0, unless the corner is
+        // the origin (the voxel's projection), where the arc is a quarter circle
+        th = (q.a > T(0) || q.c > T(0)) ? 0.0 : 0.5 * M_PI;
     } else {
+        T Q[4];
 #pragma unroll
-        for (int X = 0; X < 4; ++X) Q0[X] = pl_qedge(q, X, mb - 1);
-        s0 = Q0[0] + q.s[0];
+        for (int X = 0; X < 4; ++X) Q[X] = pl_qedge(q, X, mb - 1);
+        Q01 = Q[1]; Q02 = Q[2]; Q03 = Q[3];
+        s0 = Q[0] + q.s[0];
         kind0 = KEDGE;
-        hiS = Q0[1] > T(0);
-        loA = Q0[2] > T(0);
+        hiS = Q[1] > T(0);
+        loA = Q[2] > T(0);
+        wh0 = hiS ? sqrt_t(Q[1] + q.a2) : sqrt_t(Q[0] + q.c2);
+        wl0 = loA ? sqrt_t(Q[2] + q.c2) : sqrt_t(Q[0] + q.a2);
+        th = pl_arc_angle(q, hiS, loA, Q, wh0, wl0);
     }
-    T wh0 = hiS ? sqrt_t(Q0[1] + q.a2) : sqrt_t(Q0[0] + q.c2);
-    T wl0 = loA ? sqrt_t(Q0[2] + q.c2) : sqrt_t(Q0[0] + q.a2);
     int m = mb;
     T acc = T(0);
     for (int guard = 0; guard < 1 << 20; ++guard) {
         T Qe[4];
 #pragma unroll
         for (int X = 0; X < 4; ++X) Qe[X] = pl_qedge(q, X, m);
-        int next = KEDGE;
-        if (!hiS && Qe[1] > T(0)) next = KAD;
-        if (!loA && Qe[2] > T(0) && (next == KEDGE || q.gx < T(0))) next = KBC;
-        if (next == KEDGE && Qe[3] > T(0)) next = KBD;
-        T Q1[4], s1;
-        if (next == KEDGE) {
-#pragma unroll
-            for (int X = 0; X < 4; ++X) Q1[X] = Qe[X];
-            s1 = Qe[0] + q.s[0];
-        } else if (next == KAD) {
-            Q1[0] = q.gv; Q1[1] = T(0); Q1[2] = -q.gx; Q1[3] = -q.gu; s1 = q.s[1];
-        } else if (next == KBC) {
-            Q1[0] = q.gu; Q1[1] = q.gx; Q1[2] = T(0); Q1[3] = -q.gv; s1 = q.s[2];
-        } else {
-            Q1[0] = q.gu + q.gv; Q1[1] = q.gu; Q1[2] = q.gv; Q1[3] = T(0); s1 = q.s[3];
-        }
+        // the piece ends at the next corner inside the bin, else at its outer edge
+        const bool cad = !hiS && Qe[1] > T(0), cbc = !loA && Qe[2] > T(0);
+        const int next = (cad && (!cbc || q.gx >= T(0))) ? KAD : cbc ? KBC : (Qe[3] > T(0) ? KBD : KEDGE);
+        const bool edge = next == KEDGE, atAD = next == KAD, atBC = next == KBC;
+        // Q1[X] = s1 - s_X: at a corner Y it is s_Y - s_X
+        const T Q10 = edge ? Qe[0] : atAD ? q.gv : atBC ? q.gu : q.gu + q.gv;
+        const T Q11 = edge ? Qe[1] : atAD ? T(0) : atBC ? q.gx : q.gu;
+        const T Q12 = edge ? Qe[2] : atAD ? -q.gx : atBC ? T(0) : q.gv;
+        const T Q13 = edge ? Qe[3] : atAD ? -q.gu : atBC ? -q.gv : T(0);
         // s1 - s0 from the quantity that is exactly zero at one end
-        T dl = q.two_r0m1 + T(2 * m);
-        if (kind0 == KAC) dl = Q1[0];
-        else if (kind0 == KAD) dl = Q1[1];
-        else if (kind0 == KBC) dl = Q1[2];
-        else if (next == KAD) dl = -Q0[1];
-        else if (next == KBC) dl = -Q0[2];
-        else if (next == KBD) dl = -Q0[3];
-        // legs of the arc end points on the current hi / lo lines
-        T wh1 = hiS ? sqrt_t(Q1[1] + q.a2) : sqrt_t(Q1[0] + q.c2);
-        T wl1 = loA ? sqrt_t(Q1[2] + q.c2) : sqrt_t(Q1[0] + q.a2);
-        T xh = hiS ? wh1 : q.a, yh = hiS ? q.d : wh1;
-        T xl = loA ? q.b : wl1, yl = loA ? wl1 : q.c;
-        T chx, chy;
-        if (!hiS && !loA) {
-            chx = -sdiv(Q1[0], q.a + wl1);
-            chy = sdiv(Q1[0], wh1 + q.c);
-        } else if (!hiS) {
-            chx = q.a - q.b;
-            chy = sdiv(q.gu, wh1 + wl1);
-        } else if (!loA) {
-            chx = -sdiv(q.gv, wh1 + wl1);
-            chy = q.d - q.c;
-        } else {
-            chx = sdiv(Q1[3], wh1 + q.b);
-            chy = -sdiv(Q1[3], q.d + wl1);
-        }
-        T cross = fma(xl, chy, -yl * chx);
-        T dot = fma(xl, xh, yl * yh);
-        T th = atan2_t(cross, dot);
-        T ch = corr(hiS ? q.d : q.a, s0, dl, wh0, wh1);
-        T cl = corr(loA ? q.b : q.c, s0, dl, wl0, wl1);
-        acc += fma(dl, th, (hiS ? -ch : ch) + (loA ? -cl : cl));
+        const T dl = kind0 == KEDGE ? (edge ? q.two_r0m1 + T(2 * m) : (atAD ? -Q01 : atBC ? -Q02 : -Q03))
+                                    : (kind0 == KAC ? Q10 : kind0 == KAD ? Q11 : Q12);
+        // legs of the end points at s1 on their current lines
+        const T wh1 = sqrt_t(hiS ? Q11 + q.a2 : Q10 + q.c2);
+        const T wl1 = sqrt_t(loA ? Q12 + q.c2 : Q10 + q.a2);
+        const PlSwept<T> H = pl_swept(hiS ? q.d : q.a, s0, dl, wh0, wh1);
+        const PlSwept<T> Lo = pl_swept(loA ? q.b : q.c, s0, dl, wl0, wl1);
+        const T sh = hiS ? T(-1) : T(1), sl = loA ? T(-1) : T(1);
+        th += (double)fma(sh, H.A, sl * Lo.A);
+        acc += fma(dl, (T)th, fma(sh, H.C, sl * Lo.C));
         // advance
-#pragma unroll
-        for (int X = 0; X < 4; ++X) Q0[X] = Q1[X];
-        s0 = s1;
+        Q01 = Q11; Q02 = Q12; Q03 = Q13;
+        s0 = Q10 + q.s[0];
         kind0 = next;
-        wh0 = wh1;
-        wl0 = wl1;
-        if (next == KAD) { hiS = true; wh0 = q.a; }
-        if (next == KBC) { loA = true; wl0 = q.c; }
-        if (next == KEDGE || next == KBD) {
+        wh0 = atAD ? q.a : wh1;
+        wl0 = atBC ? q.c : wl1;
+        hiS = hiS || atAD;
+        loA = loA || atBC;
+        if (edge || next == KBD) {
             sink(m, T(0.5) * wgt * acc);
             acc = T(0);
             if (next == KBD || m >= me) break;

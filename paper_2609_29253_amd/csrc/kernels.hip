@@ -426,7 +426,7 @@ constexpr int kSparseGrid = 4096;
 template <int SHAPE, class AT, int NB, bool SPARSE = false>
 constexpr int closed_waves()
 {
-    return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 && NB >= 4 ? 2 : 3);
+    return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 ? (NB >= 4 ? 2 : 3) : (NB <= 2 ? 4 : 3));
 }
 
 // LDS histogram entries per work-group: 16 KB in FP64 at four waves (four
