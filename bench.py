@@ -23,21 +23,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A+Aᵀ voxel×transducer pairs/s, closed-form FP32 vs quadrature/FP64 at rel err"
 
-# Algorithmic FLOPs per area evaluation (one quadrant of one voxel-transducer
-# pair in one fine bin), with the per-pair and per-quadrant setup spread over
-# the evaluations: the operations of the device formulas counted one by one
-# (FMA = 2, add/mul = 1, sqrt/rsq/rcp = 1; the cylinder path calls no library
-# routine) over a sample of the 128^3 x 256-cylinder workload, where the
-# Carlson loop runs its actual number of steps.
-FLOPS_PER_EVAL = {
-    ("closed", 0, "fp32"): 106.0,   # planar, FP32 cancellation-free form (static count of the common path)
-    ("closed", 0, "fp64"): 106.0,
-    ("closed", 1, "fp32"): 282.3,   # cylinder, FP64 areas, one Newton step after each v_rsq_f64
-    ("closed", 1, "fp64"): 337.1,   # cylinder, two Newton steps
-}
-# per surface point of the quadrature (FP64 distance + bin test, FP32/FP64 weight)
-FLOPS_PER_POINT = 14.0
-
+# Algorithmic FLOPs of the dominant kernel per area evaluation (one quadrant of
+# one voxel-transducer pair in one fine bin) are read from its own instruction
+# counters, committed under profiles/ as "flops-json" lines: the FP64 and FP32
+# FMA (2 FLOP), MUL, ADD and transcendental (1 FLOP each) wave instructions of
+# one launch, times 64 lanes, times the measured lane activity
+# SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU) (the operations the active
+# lanes executed), over that launch's area evaluations.
 PEAKS = {"f32": 157.3e12, "f64": 78.6e12}
 
 
@@ -56,22 +48,51 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def profile_records(kind):
+    """The machine-readable "<kind>-json:" lines of the committed summaries."""
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        try:
+            with open(path) as fh:
+                for line in fh:
+                    if line.strip().startswith(kind + "-json:"):
+                        out.append(json.loads(line.split(":", 1)[1]))
+        except (OSError, ValueError):
+            pass
+    return out
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE, calibrated on a plain copy), or None when the kernel sources
     have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "closed_cylinder_128c_k256_counters.md")
-    try:
-        with open(path) as fh:
-            for line in fh:
-                if line.strip().startswith("traffic-json:"):
-                    rec = json.loads(line.split(":", 1)[1])
-                    if (rec["kernel"] == kernel and rec["workload"] == workload
-                            and rec["source_hash"] == kernel_source_hash()):
-                        return rec["traffic_bytes"]
-    except (OSError, ValueError, KeyError):
-        pass
+    for rec in profile_records("traffic"):
+        if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                and rec.get("source_hash") == kernel_source_hash()):
+            return rec["traffic_bytes"]
     return None
+
+
+def counter_flops(kernel, workload):
+    """(FP64 FLOPs, FP32 FLOPs) per area evaluation of ``kernel`` on ``workload``
+    from its committed instruction counters, and whether the kernel sources
+    still hash to the profiled ones; None without a record."""
+    best = None
+    for rec in profile_records("flops"):
+        if rec.get("kernel") != kernel or rec.get("workload") != workload:
+            continue
+        c = rec["counters"]
+        lam = c["SQ_THREAD_CYCLES_VALU"] / (64.0 * c["SQ_ACTIVE_INST_VALU"])
+        per = {}
+        for p in ("F64", "F32"):
+            ops = (2.0 * c[f"SQ_INSTS_VALU_FMA_{p}"] + c[f"SQ_INSTS_VALU_MUL_{p}"] + c[f"SQ_INSTS_VALU_ADD_{p}"]
+                   + c[f"SQ_INSTS_VALU_TRANS_{p}"])
+            per[p] = lam * 64.0 * ops / rec["evals_per_launch"]
+        cur = rec.get("source_hash") == kernel_source_hash()
+        if best is None or cur:
+            best = (per["F64"], per["F32"], cur, lam)
+    return best
 
 
 def log(*a):
@@ -480,7 +501,8 @@ def main():
         op.forward(coef)
         op.adjoint(y)
         torch.cuda.synchronize()
-        log(f"[bench] profile run done: one A and one A^T of {prob.name} ({args.profile_mode})")
+        log(f"[bench] profile run done: one A and one A^T of {prob.name} ({args.profile_mode}); "
+            f"{op.query(7) * B:.6e} area evaluations per launch")
         op.close()
         if args.probe:
             from paper_2609_29253_amd import _lib
@@ -496,22 +518,35 @@ def main():
     # the area kernel of A (that of A^T does the same area work and takes the same time)
     dom_ms = main_res["ms_forward"]
     dom_name = "k_fwd_closed"
-    flops = FLOPS_PER_EVAL[("closed", shape, "fp32")] * main_res["evals_per_volume"] * B
+    dom_full = (f"k_fwd_closed<{shape}, {'double' if shape == 1 else 'float'}, {min(B, 8) if B > 1 else 1}, "
+                f"float, 0, false>")
     area_dtype = "f64" if shape == 1 else "f32"
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    peak = PEAKS[area_dtype] / 1e12
-    dom_full = f"{dom_name}<{shape}, double, 1, float, 0, false>" if shape == 1 else dom_name
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom_full, prob.name),
-                "kernel": dom_name,
-                "flops_per_launch": flops, "launch_ms": round(dom_ms, 3), "area_dtype": area_dtype}
+    evals = main_res["evals_per_volume"] * B
+    fl = counter_flops(dom_full, prob.name)
+    roofline = {"bound": "alu", "achieved": None, "peak": None, "unit": "TFLOP/s", "frac": None,
+                "traffic": measured_traffic(dom_full, prob.name), "kernel": dom_full, "launch_ms": round(dom_ms, 3),
+                "area_evaluations_per_launch": evals}
+    if fl is not None:
+        f64_pe, f32_pe, current, lam = fl
+        f64, f32 = f64_pe * evals, f32_pe * evals
+        t = dom_ms * 1e-3
+        achieved = (f64 + f32) / t / 1e12
+        # the peak of this FP64/FP32 mix: the time the published peaks need for it
+        peak = (f64 + f32) / (f64 / PEAKS["f64"] + f32 / PEAKS["f32"]) / 1e12
+        roofline.update(achieved=round(achieved, 3), peak=round(peak, 2), frac=round(achieved / peak, 4),
+                        flops_per_eval={"f64": round(f64_pe, 1), "f32": round(f32_pe, 1)},
+                        flops_per_launch=f64 + f32, lane_activity=round(lam, 3),
+                        frac_f64=round(f64 / t / PEAKS["f64"], 4), frac_f32=round(f32 / t / PEAKS["f32"], 4),
+                        counters_current=current)
     # the published peak placed on this device: an FMA-only kernel built like the library's
     try:
         from paper_2609_29253_amd import _lib
         pk = _lib.probe_peak(0)
-        meas = pk["fp64_flops" if area_dtype == "f64" else "fp32_flops"] / 1e12
-        roofline["measured_fma_peak"] = round(meas, 2)
-        roofline["frac_of_measured_fma_peak"] = round(achieved / meas, 4)
+        if roofline["achieved"] is not None:
+            # the blended mix against the measured FMA ceilings of each precision
+            f64_t = roofline["frac_f64"] * PEAKS["f64"] / (pk["fp64_flops"])
+            f32_t = roofline["frac_f32"] * PEAKS["f32"] / (pk["fp32_flops"])
+            roofline["frac_of_measured_fma_peak"] = round(f64_t + f32_t, 4)
         roofline["device"] = {"compute_units": pk["compute_units"], "clock_ghz": round(pk["clock_ghz"], 3),
                               "fp64_fma_tflops": round(pk["fp64_flops"] / 1e12, 2),
                               "fp32_fma_tflops_unpacked": round(pk["fp32_flops"] / 1e12, 2)}
