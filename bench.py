@@ -130,6 +130,44 @@ def time_op(op, coef, y, steps, warmup, torch):
     return wall, f, a
 
 
+def run_tiles(prob, torch, dev, log, steps=3):
+    """A/B of the forward's two decompositions on the workload (FP32 I/O,
+    closed form): (voxel brick, transducer chunk) work-groups adding into f
+    with atomics, against (transducer, time tile) work-groups that own their
+    tile of f, at the automatic and at fixed tile widths.  Forward time only
+    (the adjoint is the same in both), HIP events on torch's current stream."""
+    from paper_2609_29253_amd.operator import PatOperator, build_kernel
+    kern = build_kernel(prob.phi_type, prob.kappa, prob.eir, prob.sound_speed, prob.fs, prob.U)
+    B = prob.coef.shape[0]
+    coef = torch.tensor(prob.coef, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream()
+    rows = []
+    ref = None
+    for tiles in (None, 0, 32, 64, 128, 256, 512):
+        op = PatOperator.from_problem(prob, mode="closed", precision="fp32", max_batch=B, kernel=kern,
+                                      time_tiles=tiles)
+        s = op.forward(coef)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in ev:
+            e0.record(st)
+            op.forward(coef)
+            e1.record(st)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        out = s.double()
+        if ref is None:
+            ref = out
+        diff = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
+        row = {"decomposition": "bricks" if tiles is None else "time tiles",
+               "tile_shells": int(op.query(9)), "automatic": tiles == 0, "ms_forward": round(ms, 3),
+               "rel_l2_vs_bricks": diff}
+        rows.append(row)
+        log(f"[bench] tiles {prob.name}: {row}")
+        op.close()
+    return {"workload": prob.name, "rows": rows}
+
+
 def run_next(args, prob, kern, B, pairs, torch, dev, log):
     """Approximate variants: time per A + A^T and rel L2 error against the
     oracle's exact method (method error) and its own version of the variant
@@ -427,6 +465,10 @@ def main():
                     help="only config 4's projected-gradient reconstruction at its stated size (192^3 voxels, "
                          "384 cylinders, 50 iterations, checkpoints every 10, a resume from iteration 40), "
                          "printed as one JSON object instead of the benchmark line")
+    ap.add_argument("--tiles", action="store_true",
+                    help="only the A/B of the forward's decompositions on the workload (voxel bricks against "
+                         "(transducer, time tile) work-groups at several tile widths), printed as one JSON "
+                         "object instead of the benchmark line")
     ap.add_argument("--pgd-dir", default=None, help="folder for the --pgd checkpoints (default: a temporary one)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only the per-configuration GPU and oracle rates (planar64_32c, cyl256_128c, planar512_256c, batch8_planar256_128c), printed as one "
@@ -451,6 +493,10 @@ def main():
         ckdir = args.pgd_dir or tempfile.mkdtemp(prefix="pgd_")
         os.makedirs(ckdir, exist_ok=True)
         print(json.dumps({"pgd": run_pgd(torch, dev, log, ckdir)}), flush=True)
+        return
+    if args.tiles:
+        dev = torch.device("cuda", 0)
+        print(json.dumps({"tiles": run_tiles(build_workload(args.workload), torch, dev, log)}), flush=True)
         return
     if args.cpu_table:
         dev = torch.device("cuda", 0)

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PATOP_ABI_VERSION 3
+#define PATOP_ABI_VERSION 4
 
 typedef enum {
     PAT_OK = 0,
@@ -129,7 +129,8 @@ typedef struct {
     int32_t quad_n2;       /* quadrature cells along the second surface coordinate */
     int32_t precision;     /* PAT_FP32 or PAT_FP64 (element type of device buffers) */
     int32_t max_batch;     /* workspace is sized for this many volumes (>= 1)      */
-    int32_t flags;         /* must be 0                                            */
+    int32_t flags;         /* 0, or PAT_FLAG_TIME_TILES with bits 8-11 = log2 of the
+                              tile width in area shells (5..9; 0 = automatic)      */
     int32_t area_step;     /* coarse area grid of Remark 1: the area of each shell of
                               area_step fine bins (bins (j-1) area_step + 1 .. j area_step)
                               is evaluated once and split evenly over its bins;
@@ -137,6 +138,16 @@ typedef struct {
                               trapezoid and table modes, 1 for quadrature          */
     int32_t reserved;      /* must be 0                                            */
 } pat_params;
+
+/* pat_params.flags: the closed-form forward (area modes closed, trapezoid and
+ * table; not quadrature, where it is refused with PAT_E_ARG) runs one
+ * work-group per (transducer, tile of consecutive area shells) that owns its
+ * tile of the fine-bin vector f_k (Eq. ui_area), instead of one per (voxel
+ * brick, transducer chunk) adding into f with atomics.  Same result to
+ * rounding (the order of the FP64 sums differs).  The work items are sorted by
+ * an estimated cost at pat_set_geometry; pat_forward_sparse and the adjoint
+ * are unchanged.  pat_query(9) returns the tile width (0 when off). */
+#define PAT_FLAG_TIME_TILES 1
 
 typedef struct pat_ctx pat_ctx;
 
@@ -214,7 +225,8 @@ pat_status pat_check_geometry(const pat_transducer* tr, int32_t K, const pat_gri
  *   7 area evaluations per volume and application (closed form: one per
  *     quadrant and fine bin; quadrature: one per surface point), counted on
  *     the device at the first request (synchronous)
- *   8 voxel-transducer pairs per volume */
+ *   8 voxel-transducer pairs per volume
+ *   9 area shells per time tile of the (transducer, time tile) forward, 0 if off */
 pat_status pat_query(const pat_ctx* ctx, int32_t what, double* out);
 
 /* Vector-ALU peak of HIP device `device` as this library's kernels are built

@@ -17,10 +17,11 @@ STATUS_NAMES = ["PAT_OK", "PAT_E_ARG", "PAT_E_FRAME", "PAT_E_SHAPE", "PAT_E_SEPA
 
 PAT_PLANAR, PAT_CYLINDER = 0, 1
 PAT_AREA_CLOSED, PAT_AREA_QUADRATURE, PAT_AREA_TRAPEZOID, PAT_AREA_LUT = 0, 1, 2, 3
-ABI_VERSION = 3
+ABI_VERSION = 4
 PAT_FP32, PAT_FP64 = 0, 1
 PAT_PHI_CONE, PAT_PHI_WENDLAND2 = 0, 1
 PAT_EIR_GAUSS_COS, PAT_EIR_SAMPLED = 0, 1
+PAT_FLAG_TIME_TILES = 1
 
 EXPORTED = ["pat_create", "pat_set_geometry", "pat_forward", "pat_forward_sparse", "pat_forward_noalloc",
             "pat_adjoint",

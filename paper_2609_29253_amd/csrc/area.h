@@ -342,7 +342,11 @@ __device__ __forceinline__ PlSwept<T> pl_swept(T p, T s0, T dl, T w0, T w1)
 // Theta(s) at an edge inside the quadrant's range, for a pass that starts
 // after the quadrant's first bin: the angle between the arc's end points from
 // one atan2 of the chord between them (cancellation free: every difference of
-// nearby squares comes from the corner offsets Q[X] = s - s_X)
+// nearby squares comes from the corner offsets Q[X] = s - s_X, and the sides
+// b - a and d - c from the FP64 differences of squares, (b^2 - a^2) / (a + b):
+// the FP32 values of a and b far from the voxel's projection (~300 radial
+// steps) would leave their difference ~1e-6 off, and Theta carries that error
+// into every later bin of the pair)
 template <class T>
 __device__ __forceinline__ double pl_arc_angle(const PlQuad<T>& q, bool hiS, bool loA, const T Q[4], T wh, T wl)
 {
@@ -353,11 +357,11 @@ __device__ __forceinline__ double pl_arc_angle(const PlQuad<T>& q, bool hiS, boo
         chx = -sdiv(Q[0], q.a + wl);
         chy = sdiv(Q[0], wh + q.c);
     } else if (!hiS) {
-        chx = q.a - q.b;
+        chx = -sdiv(q.gu, q.a + q.b);
         chy = sdiv(q.gu, wh + wl);
     } else if (!loA) {
         chx = -sdiv(q.gv, wh + wl);
-        chy = q.d - q.c;
+        chy = sdiv(q.gv, q.c + q.d);
     } else {
         chx = sdiv(Q[3], wh + q.b);
         chy = -sdiv(Q[3], q.d + wl);

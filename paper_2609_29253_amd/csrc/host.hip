@@ -100,6 +100,7 @@ struct pat_ctx {
     int32_t* d_sup = nullptr;       // support list [N], per-brick counts [nbricks], offsets [nbricks + 1],
                                     // brick order [nbricks]
     double2* d_lut = nullptr;       // E~ / F~ tables [kLutN^2] (lookup-table I_l)
+    int32_t* d_items = nullptr;     // (transducer, time tile) forward: work items of both shape groups
 };
 
 namespace {
@@ -133,7 +134,7 @@ void free_dev(pat_ctx* c)
 {
     void** ptrs[] = {(void**)&c->d_tr, (void**)&c->d_kperm, (void**)&c->d_scale, (void**)&c->d_G,
                      (void**)&c->d_qpts, (void**)&c->d_qdA, (void**)&c->d_f, &c->d_W, (void**)&c->d_z,
-                     (void**)&c->d_sup, (void**)&c->d_lut};
+                     (void**)&c->d_sup, (void**)&c->d_lut, (void**)&c->d_items};
     for (void** p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -210,8 +211,14 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (!tr || !grid || !kernel || !prm || K < 1) return fail(c, PAT_E_ARG, "null argument or K < 1");
     const pat_params& p = *prm;
     if (!(p.sound_speed > 0.0) || !(p.fs > 0.0) || !(p.t0 >= 0.0) || !std::isfinite(p.t0) || p.L < 1 || p.U < 1 ||
-        p.max_batch < 1 || p.flags != 0 || p.reserved != 0)
+        p.max_batch < 1 || p.reserved != 0)
         return fail(c, PAT_E_ARG, "invalid sampling parameters");
+    const int tile_log2 = (p.flags >> 8) & 0xF;
+    const bool tiles = (p.flags & PAT_FLAG_TIME_TILES) != 0;
+    if ((p.flags & ~(PAT_FLAG_TIME_TILES | 0xF00)) != 0 || (tile_log2 != 0 && (!tiles || tile_log2 < 5 || tile_log2 > 9)))
+        return fail(c, PAT_E_ARG, "invalid flags");
+    if (tiles && p.area_mode == PAT_AREA_QUADRATURE)
+        return fail(c, PAT_E_ARG, "the time-tile forward serves the closed-form area modes");
     if (p.U > kMaxU) return fail(c, PAT_E_UNSUPPORTED, "U above 65536");
     if (p.area_mode != PAT_AREA_CLOSED && p.area_mode != PAT_AREA_QUADRATURE && p.area_mode != PAT_AREA_TRAPEZOID &&
         p.area_mode != PAT_AREA_LUT)
@@ -471,6 +478,64 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         Lp.sup_order = c->d_sup + N + 2 * nbricks + 1;
     }
 
+    // ---- (transducer, time tile) forward: tile width, and each shape group's
+    // work items sorted by estimated cost, largest first
+    if (tiles) {
+        const int64_t J = B.Jhi - B.Jlo + 1;
+        int tile = tile_log2 ? 1 << tile_log2 : 512;
+        // automatic: the widest tile (at most 512 shells) that still gives
+        // 4096 work items, about four per work-group slot of the device
+        if (!tile_log2)
+            while (tile > 32 && (int64_t)K * ((J + tile - 1) / tile) < 4096) tile >>= 1;
+        const int64_t ntiles = (J + tile - 1) / tile;
+        if ((int64_t)K * ntiles >= (int64_t)1 << 31) {
+            free_dev(c);
+            return fail(c, PAT_E_UNSUPPORTED, "too many time tiles");
+        }
+        const size_t nit = (size_t)K * ntiles;
+        double* d_cost = nullptr;
+        if (hipMalloc((void**)&c->d_items, sizeof(int32_t) * nit) != hipSuccess ||
+            hipMalloc((void**)&d_cost, sizeof(double) * nit) != hipSuccess) {
+            (void)hipGetLastError();
+            if (d_cost) (void)hipFree(d_cost);
+            free_dev(c);
+            return fail(c, PAT_E_OOM, "device allocation failed");
+        }
+        c->ws_bytes += sizeof(int32_t) * nit;
+        e = hipMemset(d_cost, 0, sizeof(double) * nit);
+        size_t koff = 0;
+        for (int g = 0; g < Lp.ngroups && e == hipSuccess; ++g) {
+            KParams P = B;
+            P.kperm = Lp.groups[g].kperm;
+            P.nk = Lp.groups[g].nk;
+            e = launch_tile_cost(P, nbricks, tile, (int)ntiles, d_cost + koff * ntiles, nullptr);
+            koff += Lp.groups[g].nk;
+        }
+        std::vector<double> cost(nit);
+        if (e == hipSuccess) e = hipMemcpy(cost.data(), d_cost, sizeof(double) * nit, hipMemcpyDeviceToHost);
+        (void)hipFree(d_cost);
+        std::vector<int32_t> items(nit);
+        koff = 0;
+        for (int g = 0; g < Lp.ngroups; ++g) {
+            const size_t n = (size_t)Lp.groups[g].nk * ntiles;
+            int32_t* it = items.data() + koff * ntiles;
+            const double* cg = cost.data() + koff * ntiles;
+            for (size_t i = 0; i < n; ++i) it[i] = (int32_t)i;
+            std::stable_sort(it, it + n, [&](int32_t a, int32_t b) { return cg[a] > cg[b]; });
+            Lp.groups[g].items = c->d_items + koff * ntiles;
+            Lp.groups[g].nitems = (int)n;
+            koff += Lp.groups[g].nk;
+        }
+        if (e == hipSuccess) e = hipMemcpy(c->d_items, items.data(), sizeof(int32_t) * nit, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            std::string msg = std::string("time-tile set-up failed: ") + hipGetErrorString(e);
+            free_dev(c);
+            return fail(c, PAT_E_DEVICE, msg);
+        }
+        Lp.tile = tile;
+        Lp.ntiles = (int)ntiles;
+    }
+
     c->K = K;
     c->N = N;
     c->L = p.L;
@@ -557,6 +622,7 @@ pat_status pat_query(const pat_ctx* c, int32_t what, double* out)
     case 3: *out = (double)c->plan.base.Mlo; return PAT_OK;
     case 4: *out = c->truncated ? 1.0 : 0.0; return PAT_OK;
     case 5: *out = (double)c->ws_bytes; return PAT_OK;
+    case 9: *out = (double)c->plan.tile; return PAT_OK;
     case 7:
     case 8: {
         pat_ctx* m = const_cast<pat_ctx*>(c);

@@ -12,6 +12,8 @@ struct ShapeGroup {
     const int32_t* kperm;   // device array of transducer indices
     int nk;
     int kchunk_fwd, kchunk_adj;
+    const int32_t* items;   // (transducer, time tile) forward: items kk ntiles + t, largest estimated cost
+    int nitems;             // first (nk ntiles of them); null when that forward is off
 };
 
 struct LaunchPlan {
@@ -34,6 +36,8 @@ struct LaunchPlan {
     int32_t* sup_cnt;       // [nbricks] nonzero voxels per brick (in sup_order)
     int32_t* sup_off;       // [nbricks + 1] their exclusive prefix sums (last entry: total)
     const int32_t* sup_order;   // [nbricks] brick indices in Morton order (the list's brick order)
+    int tile, ntiles;       // (transducer, time tile) forward: shells per tile and tiles per transducer
+                            // (tile = 0: the brick forward)
 };
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);
@@ -42,6 +46,9 @@ hipError_t launch_forward_sparse(const LaunchPlan& L, const void* coef, void* si
 // the E~ / F~ tables of the lookup-table I_l: kLutN^2 nodes {E~, F~}
 hipError_t launch_lut_build(double2* table, hipStream_t s);
 hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_t s);
+// estimated work of the (transducer, time tile) items of one shape group (P.kperm, P.nk):
+// cost[kk ntiles + t] += shells of each brick window inside tile t (cost zeroed by the caller)
+hipError_t launch_tile_cost(const KParams& P, int nbricks, int tile, int ntiles, double* cost, hipStream_t s);
 hipError_t launch_adjoint(const LaunchPlan& L, const void* sig, void* coef, int B, hipStream_t s);
 
 }  // namespace patop

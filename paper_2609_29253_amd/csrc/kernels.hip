@@ -63,6 +63,19 @@ struct Brick {
     double lo[3], hi[3];   // axis-aligned box of the brick's voxel centres (global)
 };
 
+// axis-aligned box of brick bid's voxel centres (global coordinates)
+__device__ __forceinline__ void brick_box(const KParams& P, int bid, double lo[3], double hi[3])
+{
+    const int bxi = bid % P.nbx, byi = (bid / P.nbx) % P.nby, bzi = bid / (P.nbx * P.nby);
+    const int x0 = bxi * kBrickX, y0 = byi * kBrickY, z0 = bzi * kBrickZ;
+    const int x1 = (int)min((int64_t)(x0 + kBrickX), P.n[0]) - 1;
+    const int y1 = (int)min((int64_t)(y0 + kBrickY), P.n[1]) - 1;
+    const int z1 = (int)min((int64_t)(z0 + kBrickZ), P.n[2]) - 1;
+    lo[0] = P.origin[0] + x0 * P.w; hi[0] = P.origin[0] + x1 * P.w;
+    lo[1] = P.origin[1] + y0 * P.w; hi[1] = P.origin[1] + y1 * P.w;
+    lo[2] = P.origin[2] + z0 * P.w; hi[2] = P.origin[2] + z1 * P.w;
+}
+
 __device__ __forceinline__ void brick_setup(const KParams& P, int bid, Brick& Bk)
 {
     const int bxi = bid % P.nbx, byi = (bid / P.nbx) % P.nby, bzi = bid / (P.nbx * P.nby);
@@ -76,12 +89,7 @@ __device__ __forceinline__ void brick_setup(const KParams& P, int bid, Brick& Bk
     Bk.iz = z0 + (l >> 4);
     Bk.valid = Bk.ix < P.n[0] && Bk.iy < P.n[1] && Bk.iz < P.n[2];
     Bk.idx = Bk.valid ? Bk.ix + P.n[0] * (Bk.iy + P.n[1] * (int64_t)Bk.iz) : 0;
-    const int x1 = (int)min((int64_t)(x0 + kBrickX), P.n[0]) - 1;
-    const int y1 = (int)min((int64_t)(y0 + kBrickY), P.n[1]) - 1;
-    const int z1 = (int)min((int64_t)(z0 + kBrickZ), P.n[2]) - 1;
-    Bk.lo[0] = P.origin[0] + x0 * P.w; Bk.hi[0] = P.origin[0] + x1 * P.w;
-    Bk.lo[1] = P.origin[1] + y0 * P.w; Bk.hi[1] = P.origin[1] + y1 * P.w;
-    Bk.lo[2] = P.origin[2] + z0 * P.w; Bk.hi[2] = P.origin[2] + z1 * P.w;
+    brick_box(P, bid, Bk.lo, Bk.hi);
 }
 
 // Sparse forward: group g is entries 256 g .. 256 g + 255 (< total) of the
@@ -112,16 +120,18 @@ __device__ __forceinline__ void brick_setup_sparse(const KParams& P, int64_t g, 
     }
 }
 
-// bins that any voxel of the brick can reach on transducer T (bounding sphere)
-__device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, const TrDev& T, int& wlo,
-                                             int& whi)
+// shells that any voxel of the box [lo, hi] can reach on transducer T
+// (bounding sphere; Eq. rmin_rmax bounds each pair's range inside it), clipped
+// to the kept shells [Jlo, Jhi]: empty (wlo > whi) if none
+__device__ __forceinline__ void box_window(const KParams& P, const double lo3[3], const double hi3[3],
+                                           const TrDev& T, int& wlo, int& whi)
 {
     double dd = 0.0, dm = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double o = fmax(0.0, fmax(Bk.lo[a] - T.cen[a], T.cen[a] - Bk.hi[a]));
+        double o = fmax(0.0, fmax(lo3[a] - T.cen[a], T.cen[a] - hi3[a]));
         dd += o * o;
-        double f = fmax(fabs(Bk.lo[a] - T.cen[a]), fabs(Bk.hi[a] - T.cen[a]));
+        double f = fmax(fabs(lo3[a] - T.cen[a]), fabs(hi3[a] - T.cen[a]));
         dm += f * f;
     }
     double dlo = fmax(sqrt(dd) - T.rad, 0.0), dhi = sqrt(dm) + T.rad;
@@ -131,6 +141,12 @@ __device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, 
     hi = min(hi, P.Jhi);
     wlo = (int)lo;
     whi = (int)hi;
+}
+
+__device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, const TrDev& T, int& wlo,
+                                             int& whi)
+{
+    box_window(P, Bk.lo, Bk.hi, T, wlo, whi);
 }
 
 // frame coordinates of a voxel (Sec. 4.1 / Sec. 4.2 frames), FP64
@@ -458,6 +474,113 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) 
         brick_setup_sparse(P, it / nchunks, total, Bk);
         const int kbeg = (int)(it % nchunks) * P.kchunk;
         fwd_brick<SHAPE, AT, NB, Real, IL, closed_hist<SHAPE, AT, NB, SPARSE>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward, closed-form areas, by (transducer, time tile): output-stationary
+// ---------------------------------------------------------------------------
+
+// One work-group per (transducer, tile of `tile` consecutive shells).  It owns
+// the tile's fine bins of f for every volume of the launch, so f needs neither
+// a fill nor atomics: the group scans the bricks, keeps those whose window
+// meets the tile, and for each runs the pair setup and the sweep clipped to
+// the tile into its LDS histogram, then stores the tile.  Work items come in
+// the order of items[] (estimated cost, largest first) so that the in-order
+// dispatch of work-groups balances the tail of the launch.
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_fwd_tile(
+    KParams P, const int32_t* __restrict__ items, int tile, int ntiles, int nbricks, const Real* __restrict__ coef,
+    double* __restrict__ f)
+{
+    extern __shared__ double hist[];   // [NB][tile]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
+    __shared__ int cand[kThreads];
+    __shared__ int ncand;
+    const int item = items[blockIdx.x];
+    const int kk = item / ntiles, t = item - kk * ntiles;
+    const int k = P.kperm[kk];
+    const int tlo = (int)P.Jlo + t * tile;
+    const int thi = min((int)P.Jhi, tlo + tile - 1);
+    for (int i = threadIdx.x; i < NB * tile; i += kThreads) hist[i] = 0.0;
+    for (int c0 = 0; c0 < nbricks; c0 += kThreads) {
+        const int b = c0 + threadIdx.x;
+        bool hit = false;
+        if (b < nbricks) {
+            double lo[3], hi[3];
+            brick_box(P, b, lo, hi);
+            int wlo, whi;
+            box_window(P, lo, hi, P.tr[k], wlo, whi);
+            hit = wlo <= thi && whi >= tlo;
+        }
+        __syncthreads();   // the previous list has been consumed (the histogram cleared)
+        if (threadIdx.x == 0) ncand = 0;
+        __syncthreads();
+        if (hit) cand[atomicAdd(&ncand, 1)] = b;
+        __syncthreads();
+        const int nc = ncand;
+        for (int i = 0; i < nc; ++i) {
+            Brick Bk;
+            brick_setup(P, cand[i], Bk);
+            double p0[NB];
+            bool nz = false;
+#pragma unroll
+            for (int v = 0; v < NB; ++v) {
+                p0[v] = Bk.valid ? (double)coef[v * P.N + Bk.idx] : 0.0;
+                nz |= p0[v] != 0.0;
+            }
+            if (!__syncthreads_or(nz)) continue;
+            typename PairOf<SHAPE, AT, Real, IL>::type pair;
+            pair.bind(box, P.lut);
+            {
+                const TrDev T = P.tr[k];
+                double x[3];
+                frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+                pair.setup(T, x, P.r0);
+            }
+            if (nz) {
+                auto sink = [&](int m, auto area) {
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) atomicAdd(&hist[v * tile + (m - tlo)], p0[v] * (double)area);
+                };
+                pair.sweep(tlo, thi, sink, P.r0);
+            }
+        }
+    }
+    __syncthreads();
+    // shell j holds the fine bins (j - 1) step + 1 .. j step, its area split
+    // evenly over them (Remark 1), as in the brick kernels
+    const int S = P.step;
+    const int64_t Mhi = P.Mlo + P.Mcount - 1;
+    const int wn = thi - tlo + 1;
+    for (int i = threadIdx.x; i < wn * S; i += kThreads) {
+        const int jj = i / S;
+        const int64_t m = (int64_t)(tlo + jj - 1) * S + 1 + (i - jj * S);
+        if (m < P.Mlo || m > Mhi) continue;
+#pragma unroll
+        for (int v = 0; v < NB; ++v) f[((int64_t)v * P.K + k) * P.Mcount + (m - P.Mlo)] = hist[v * tile + jj] * S;
+    }
+}
+
+// Estimated work of each (transducer, time tile) item of a shape group: the
+// shells of every brick's window that fall in the tile, summed over the bricks
+// (integers, so the FP64 sums are exact and independent of their order).
+// One thread per (brick, transducer); cost[kk ntiles + t].
+__global__ __launch_bounds__(kThreads) void k_tile_cost(KParams P, int nbricks, int tile, int ntiles,
+                                                        double* __restrict__ cost)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g >= (int64_t)nbricks * P.nk) return;
+    const int b = (int)(g % nbricks), kk = (int)(g / nbricks);
+    double lo[3], hi[3];
+    brick_box(P, b, lo, hi);
+    int wlo, whi;
+    box_window(P, lo, hi, P.tr[P.kperm[kk]], wlo, whi);
+    if (wlo > whi) return;
+    const int J0 = (int)P.Jlo;
+    for (int t = (wlo - J0) / tile; t <= (whi - J0) / tile; ++t) {
+        const int a = max(wlo, J0 + t * tile), z = min(whi, J0 + t * tile + tile - 1);
+        atomicAdd(&cost[(int64_t)kk * ntiles + t], (double)(z - a + 1));
     }
 }
 
@@ -875,6 +998,31 @@ hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, 
 }
 
 template <int SHAPE, class AT, class Real, int IL>
+hipError_t fwd_tile_nb(int nb, const KParams& P, const int32_t* items, int nitems, int tile, int ntiles,
+                       int nbricks, const Real* coef, double* f, hipStream_t s)
+{
+    const size_t sh = (size_t)nb * tile * sizeof(double);
+    switch (nb) {
+    case 1: k_fwd_tile<SHAPE, AT, 1, Real, IL><<<nitems, kThreads, sh, s>>>(P, items, tile, ntiles, nbricks, coef, f); break;
+    case 2: k_fwd_tile<SHAPE, AT, 2, Real, IL><<<nitems, kThreads, sh, s>>>(P, items, tile, ntiles, nbricks, coef, f); break;
+    case 4: k_fwd_tile<SHAPE, AT, 4, Real, IL><<<nitems, kThreads, sh, s>>>(P, items, tile, ntiles, nbricks, coef, f); break;
+    default: k_fwd_tile<SHAPE, AT, 8, Real, IL><<<nitems, kThreads, sh, s>>>(P, items, tile, ntiles, nbricks, coef, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <class Real>
+hipError_t fwd_tile_cyl(int mode, int nb, const KParams& P, const int32_t* items, int nitems, int tile, int ntiles,
+                        int nbricks, const Real* coef, double* f, hipStream_t s)
+{
+    if (mode == 2)
+        return fwd_tile_nb<1, double, Real, kIlTrapezoid>(nb, P, items, nitems, tile, ntiles, nbricks, coef, f, s);
+    if (mode == 3)
+        return fwd_tile_nb<1, double, Real, kIlTable>(nb, P, items, nitems, tile, ntiles, nbricks, coef, f, s);
+    return fwd_tile_nb<1, double, Real, kIlExact>(nb, P, items, nitems, tile, ntiles, nbricks, coef, f, s);
+}
+
+template <int SHAPE, class AT, class Real, int IL>
 hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
                          hipStream_t s)
 {
@@ -948,9 +1096,13 @@ template <class Real>
 hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hipStream_t s, bool sparse)
 {
     hipError_t e;
-    const int64_t nf = (int64_t)B * L.base.K * L.base.Mcount;
-    k_fill<<<grid_fill_blocks(nf), 256, 0, s>>>(L.f, nf);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the (transducer, time tile) forward stores every fine bin of f itself
+    const bool tiles = L.tile > 0 && !sparse && L.mode != 1;
+    if (!tiles) {
+        const int64_t nf = (int64_t)B * L.base.K * L.base.Mcount;
+        k_fill<<<grid_fill_blocks(nf), 256, 0, s>>>(L.f, nf);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (sparse) {
         // support of the whole batch: the voxels with a nonzero coefficient in any volume
         k_support_count<Real><<<L.nbricks, kThreads, 0, s>>>(L.base, coef, B, L.sup_order, L.sup_cnt);
@@ -977,6 +1129,11 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
                 grid = dim3(kSparseGrid, 1);
             }
             if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
+            else if (tiles && G.shape == 0)
+                e = fwd_tile_nb<0, Real, Real, kIlExact>(nb, P, G.items, G.nitems, L.tile, L.ntiles, L.nbricks, cb,
+                                                         fb, s);
+            else if (tiles)
+                e = fwd_tile_cyl<Real>(L.mode, nb, P, G.items, G.nitems, L.tile, L.ntiles, L.nbricks, cb, fb, s);
             else if (sparse && G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact, true>(nb, grid, P, cb, fb, s);
             else if (sparse) e = fwd_cyl<Real, true>(L.mode, nb, grid, P, cb, fb, s);
             else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact>(nb, grid, P, cb, fb, s);
@@ -1047,6 +1204,13 @@ hipError_t launch_count(const LaunchPlan& L, unsigned long long* out, hipStream_
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_tile_cost(const KParams& P, int nbricks, int tile, int ntiles, double* cost, hipStream_t s)
+{
+    const int64_t n = (int64_t)nbricks * P.nk;
+    k_tile_cost<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(P, nbricks, tile, ntiles, cost);
+    return hipGetLastError();
 }
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s)

@@ -57,7 +57,7 @@ class PatOperator:
 
     def __init__(self, packed, n, origin, spacing, h, n_first, kappa, sound_speed, fs, t0, L_, U=1,
                  mode: str = "closed", quad_n: Sequence[int] = (16, 16), precision: str = "fp32",
-                 max_batch: int = 1, device: int = 0, area_step: int = 1):
+                 max_batch: int = 1, device: int = 0, area_step: int = 1, time_tiles=None):
         self.K = len(packed)
         self.n = tuple(int(v) for v in n)
         self.N = self.n[0] * self.n[1] * self.n[2]
@@ -86,19 +86,27 @@ class PatOperator:
         p.quad_n1, p.quad_n2 = int(quad_n[0]), int(quad_n[1])
         p.precision = L.PAT_FP32 if precision == "fp32" else L.PAT_FP64
         p.max_batch = self.max_batch
-        p.flags = 0
+        # time_tiles: None (brick forward), 0 (time-tile forward, automatic tile
+        # width) or the tile width in area shells (a power of two, 32..512)
+        if time_tiles is None:
+            p.flags = 0
+        else:
+            t = int(time_tiles)
+            if t and (t < 32 or t > 512 or t & (t - 1)):
+                raise ValueError("time_tiles must be 0 or a power of two in 32..512")
+            p.flags = L.PAT_FLAG_TIME_TILES | ((t.bit_length() - 1) << 8 if t else 0)
         st = L.lib().pat_set_geometry(self._ctx, arr, self.K, ctypes.byref(g), ctypes.byref(kern), ctypes.byref(p))
         L.check(st, self._ctx)
 
     @classmethod
     def from_problem(cls, prob, mode="closed", precision="fp32", max_batch=None, device=0, kernel=None,
-                     area_step=None):
+                     area_step=None, time_tiles=None):
         h, nf = kernel if kernel is not None else build_kernel(prob.phi_type, prob.kappa, prob.eir,
                                                                prob.sound_speed, prob.fs, prob.U)
         B = max_batch if max_batch is not None else (prob.coef.shape[0] if prob.coef is not None else 1)
         return cls(prob.tr.packed, prob.grid.n, prob.grid.origin, prob.grid.spacing, h, nf, prob.kappa,
                    prob.sound_speed, prob.fs, prob.t0, prob.L, prob.U, mode, prob.quad_n, precision, B, device,
-                   getattr(prob, "area_step", 1) if area_step is None else area_step)
+                   getattr(prob, "area_step", 1) if area_step is None else area_step, time_tiles)
 
     def query(self, what: int) -> float:
         out = ctypes.c_double(0.0)

@@ -52,6 +52,28 @@ def row_ratio(got, ref):
     return worst
 
 
+def ulp_distance32(a, b):
+    """Largest distance in units in the last place between two float32 arrays."""
+    ia = a.view(np.int32).astype(np.int64)
+    ib = b.view(np.int32).astype(np.int64)
+    # map the sign-magnitude order of IEEE floats onto the integers
+    ia = np.where(ia < 0, -(ia & 0x7FFFFFFF), ia)
+    ib = np.where(ib < 0, -(ib & 0x7FFFFFFF), ib)
+    return int(np.max(np.abs(ia - ib))) if a.size else 0
+
+
+def fp32_repeat_ok(a, b, floor=1e-13):
+    """Largest ulp distance over the samples that are not within `floor` of
+    their row's largest magnitude of each other (0 if all are)."""
+    a2, b2 = a.reshape(-1, a.shape[-1]), b.reshape(-1, b.shape[-1])
+    worst = 0
+    for x, y in zip(a2, b2):
+        scale = float(np.max(np.abs(x.astype(np.float64))))
+        far = np.abs(x.astype(np.float64) - y.astype(np.float64)) > floor * scale
+        worst = max(worst, ulp_distance32(x[far], y[far]))
+    return worst
+
+
 @pytest.fixture(scope="session")
 def gpu():
     import torch

@@ -20,32 +20,11 @@ import pytest
 import torch
 
 import pat_inputs as P
+from conftest import fp32_repeat_ok, ulp_distance32
 
 pytestmark = pytest.mark.gpu
 
 DT = {"fp32": torch.float32, "fp64": torch.float64}
-
-
-def ulp_distance32(a, b):
-    """Largest distance in units in the last place between two float32 arrays."""
-    ia = a.view(np.int32).astype(np.int64)
-    ib = b.view(np.int32).astype(np.int64)
-    # map the sign-magnitude order of IEEE floats onto the integers
-    ia = np.where(ia < 0, -(ia & 0x7FFFFFFF), ia)
-    ib = np.where(ib < 0, -(ib & 0x7FFFFFFF), ib)
-    return int(np.max(np.abs(ia - ib))) if a.size else 0
-
-
-def fp32_repeat_ok(a, b):
-    """Largest ulp distance over the samples that are not within 1e-13 of their
-    row's largest magnitude of each other (0 if all are)."""
-    a2, b2 = a.reshape(-1, a.shape[-1]), b.reshape(-1, b.shape[-1])
-    worst = 0
-    for x, y in zip(a2, b2):
-        scale = float(np.max(np.abs(x.astype(np.float64))))
-        far = np.abs(x.astype(np.float64) - y.astype(np.float64)) > 1e-13 * scale
-        worst = max(worst, ulp_distance32(x[far], y[far]))
-    return worst
 
 
 def twice(p, prec, mode="closed", runs=3):
