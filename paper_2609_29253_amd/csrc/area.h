@@ -377,12 +377,16 @@ __device__ __forceinline__ double pl_arc_angle(const PlQuad<T>& q, bool hiS, boo
 // bin's area, and Theta is carried from piece to piece by the angles the end
 // points sweep (in FP64), so no piece evaluates an inverse trigonometric
 // function of its own.  The piece's kind of end and its squared-radius offsets
-// are chosen by selects, not branches.
-template <class T, class Sink>
+// are chosen by selects, not branches.  FROM_FIRST: the walk starts at the
+// quadrant's first bin whatever wlo and hands only the bins from wlo on to the
+// sink, so that Theta is carried exactly as in a walk over the whole range
+// (a walk that starts later takes Theta from one atan2, accurate to FP32
+// rounding, but that error then persists over the pair's remaining bins).
+template <bool FROM_FIRST = false, class T, class Sink>
 __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T wgt, Sink& sink)
 {
-    const int mb = max(q.mfirst, wlo), me = min(q.mlast, whi);
-    if (mb > me) return;
+    const int mb = FROM_FIRST ? q.mfirst : max(q.mfirst, wlo), me = min(q.mlast, whi);
+    if (mb > me || q.mlast < wlo) return;
     // state at the start of the piece: offsets Q0[X] = s0 - s_X (X = AD, BC, BD),
     // s0, the kind of start, which lines the end points are on, their legs, Theta
     T Q01, Q02, Q03, s0, wh0, wl0;
@@ -448,7 +452,7 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
         hiS = hiS || atAD;
         loA = loA || atBC;
         if (edge || next == KBD) {
-            sink(m, T(0.5) * wgt * acc);
+            if (!FROM_FIRST || m >= wlo) sink(m, T(0.5) * wgt * acc);
             acc = T(0);
             if (next == KBD || m >= me) break;
             ++m;

@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "geometry.h"
 #include "kernels.h"
 #include "patop.h"
@@ -37,6 +39,16 @@ constexpr size_t kScratchBytes = size_t(64) << 20;
 static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace {
+
+// roctx range over one C-ABI call (host side: it brackets the validation and
+// the enqueue of the call's kernels, which a profiler's kernel trace then
+// attributes to it; no cost without a profiler attached)
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 constexpr int kMaxDevices = 64;
 
@@ -203,6 +215,7 @@ void pat_destroy(pat_ctx* c)
 pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, const pat_grid* grid,
                             const pat_kernel* kernel, const pat_params* prm)
 {
+    Range r("pat_set_geometry");
     if (!c) return PAT_E_ARG;
     DevGuard guard(c->device);
     if (!guard.ok) return fail(c, PAT_E_DEVICE, "hipSetDevice failed");
@@ -483,10 +496,13 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
     if (tiles) {
         const int64_t J = B.Jhi - B.Jlo + 1;
         int tile = tile_log2 ? 1 << tile_log2 : 512;
-        // automatic: the widest tile (at most 512 shells) that still gives
-        // 4096 work items, about four per work-group slot of the device
+        // automatic: the widest tile in 128..512 shells that still gives 8192
+        // work items (eight per work-group slot of the device, for the balance
+        // of items whose costs differ by orders of magnitude); narrower tiles
+        // repeat each pair's setup in more tiles (measured on 128^3 x 256
+        // cylinders and 256^3 x 512 planar elements: 128 and 256 are best)
         if (!tile_log2)
-            while (tile > 32 && (int64_t)K * ((J + tile - 1) / tile) < 4096) tile >>= 1;
+            while (tile > 128 && (int64_t)K * ((J + tile - 1) / tile) < 8192) tile >>= 1;
         const int64_t ntiles = (J + tile - 1) / tile;
         if ((int64_t)K * ntiles >= (int64_t)1 << 31) {
             free_dev(c);
@@ -569,21 +585,25 @@ static pat_status run(pat_ctx* c, const void* in, void* out, int32_t batch, void
 
 pat_status pat_forward(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
 {
+    Range r("pat_forward");
     return run(c, coef, signal, batch, stream, Op::forward);
 }
 
 pat_status pat_forward_sparse(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
 {
+    Range r("pat_forward_sparse");
     return run(c, coef, signal, batch, stream, Op::forward_sparse);
 }
 
 pat_status pat_adjoint(pat_ctx* c, const void* signal, void* coef, int32_t batch, void* stream)
 {
+    Range r("pat_adjoint");
     return run(c, signal, coef, batch, stream, Op::adjoint);
 }
 
 pat_status pat_forward_noalloc(pat_ctx* c, const void* coef, void* signal, int32_t batch, void* stream)
 {
+    Range r("pat_forward_noalloc");
     if (!c) return PAT_E_ARG;
     if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
     if (!coef || !signal || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
