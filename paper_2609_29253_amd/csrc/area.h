@@ -208,6 +208,16 @@ struct AtanPair {
 template <class T> struct AtanMx;
 
 template <> struct AtanMx<float> {
+    static constexpr float kSmall = 0.25f;   // eval halves the angle from here on
+    // x < kSmall: the series alone, which is what eval computes there
+    static __device__ __forceinline__ AtanPair<float> small(float x)
+    {
+        float y = x * x;
+        float p = fmaf(y, fmaf(y, fmaf(y, fmaf(y, fmaf(y, -1.0f / 13, 1.0f / 11), -1.0f / 9), 1.0f / 7), -1.0f / 5),
+                       1.0f / 3);
+        const float t = -x * y * p;
+        return {t, x + t};
+    }
     static __device__ __forceinline__ AtanPair<float> eval(float x)
     {
         if (x > 4.0f) {
@@ -235,6 +245,25 @@ template <> struct AtanMx<float> {
 };
 
 template <> struct AtanMx<double> {
+    static constexpr double kSmall = 0.1;    // eval halves the angle from here on
+    // x < kSmall: the series alone, which is what eval computes there
+    static __device__ __forceinline__ AtanPair<double> small(double x)
+    {
+        double y = x * x;
+        double p = 1.0 / 23;
+        p = fma(y, p, -1.0 / 21);
+        p = fma(y, p, 1.0 / 19);
+        p = fma(y, p, -1.0 / 17);
+        p = fma(y, p, 1.0 / 15);
+        p = fma(y, p, -1.0 / 13);
+        p = fma(y, p, 1.0 / 11);
+        p = fma(y, p, -1.0 / 9);
+        p = fma(y, p, 1.0 / 7);
+        p = fma(y, p, -1.0 / 5);
+        p = fma(y, p, 1.0 / 3);
+        const double t = -x * y * p;
+        return {t, x + t};
+    }
     static __device__ __forceinline__ AtanPair<double> eval(double x)
     {
         if (x > 4.0) {
@@ -315,8 +344,6 @@ __device__ __forceinline__ T pl_qedge(const PlQuad<T>& q, int X, int m)
     return t * (t + q.twoD[X]);
 }
 
-enum { KEDGE = 0, KAC = 1, KAD = 2, KBC = 3, KBD = 4 };
-
 // One arc end point moving along its line (at distance p from the origin, leg
 // w along the line) between in-plane squared radii s0 and s1 = s0 + dl:
 //   dw = w1 - w0 = dl / (w0 + w1),   x = tan(angle swept) = p dw / (p^2 + w0 w1),
@@ -330,13 +357,22 @@ struct PlSwept {
 };
 
 template <class T>
-__device__ __forceinline__ PlSwept<T> pl_swept(T p, T s0, T dl, T w0, T w1)
+struct PlStep {
+    T x, dw;
+};
+
+template <class T>
+__device__ __forceinline__ PlStep<T> pl_step(T p, T dl, T w0, T w1)
 {
     const T tiny = T(1e-30);
     const T dw = dl * rcp_t(fmax(w0 + w1, tiny));
-    const T x = p * dw * rcp_t(fmax(fma(p, p, w0 * w1), tiny));
-    const AtanPair<T> at = AtanMx<T>::eval(x);
-    return {fma(s0, at.mx, -x * w0 * dw), at.a};
+    return {p * dw * rcp_t(fmax(fma(p, p, w0 * w1), tiny)), dw};
+}
+
+template <class T>
+__device__ __forceinline__ PlSwept<T> pl_swept(const PlStep<T>& st, T s0, T w0, const AtanPair<T>& at)
+{
+    return {fma(s0, at.mx, -st.x * w0 * st.dw), at.a};
 }
 
 // Theta(s) at an edge inside the quadrant's range, for a pass that starts
@@ -390,13 +426,13 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
     // state at the start of the piece: offsets Q0[X] = s0 - s_X (X = AD, BC, BD),
     // s0, the kind of start, which lines the end points are on, their legs, Theta
     T Q01, Q02, Q03, s0, wh0, wl0;
-    int kind0;
+    bool k0e, k0a, k0b;   // the piece starts at a bin edge, at corner (a, d), at (b, c); else at (a, c)
     bool hiS, loA;
     double th;
     if (mb == q.mfirst) {
         Q01 = -q.gv; Q02 = -q.gu; Q03 = -(q.gu + q.gv);
         s0 = q.s[0];
-        kind0 = KAC;
+        k0e = k0a = k0b = false;
         hiS = false;
         loA = false;
         wh0 = q.c;
@@ -410,7 +446,8 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
         for (int X = 0; X < 4; ++X) Q[X] = pl_qedge(q, X, mb - 1);
         Q01 = Q[1]; Q02 = Q[2]; Q03 = Q[3];
         s0 = Q[0] + q.s[0];
-        kind0 = KEDGE;
+        k0e = true;
+        k0a = k0b = false;
         hiS = Q[1] > T(0);
         loA = Q[2] > T(0);
         wh0 = hiS ? sqrt_t(Q[1] + q.a2) : sqrt_t(Q[0] + q.c2);
@@ -423,38 +460,63 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
         T Qe[4];
 #pragma unroll
         for (int X = 0; X < 4; ++X) Qe[X] = pl_qedge(q, X, m);
-        // the piece ends at the next corner inside the bin, else at its outer edge
+        const T dlE = q.two_r0m1 + T(2 * m);   // from edge to edge
+        // the piece ends at the next corner inside the bin, else at its outer
+        // edge; every choice below is a chain of selects between values that
+        // are all computed (the common case has no divergent branch)
         const bool cad = !hiS && Qe[1] > T(0), cbc = !loA && Qe[2] > T(0);
-        const int next = (cad && (!cbc || q.gx >= T(0))) ? KAD : cbc ? KBC : (Qe[3] > T(0) ? KBD : KEDGE);
-        const bool edge = next == KEDGE, atAD = next == KAD, atBC = next == KBC;
+        const bool atAD = cad && (!cbc || q.gx >= T(0));
+        const bool atBC = cbc && !atAD;
+        const bool atBD = !cad && !cbc && Qe[3] > T(0);
+        const bool edge = !cad && !cbc && !atBD;
         // Q1[X] = s1 - s_X: at a corner Y it is s_Y - s_X
-        const T Q10 = edge ? Qe[0] : atAD ? q.gv : atBC ? q.gu : q.gu + q.gv;
-        const T Q11 = edge ? Qe[1] : atAD ? T(0) : atBC ? q.gx : q.gu;
-        const T Q12 = edge ? Qe[2] : atAD ? -q.gx : atBC ? T(0) : q.gv;
-        const T Q13 = edge ? Qe[3] : atAD ? -q.gu : atBC ? -q.gv : T(0);
+        T Q10 = q.gu + q.gv, Q11 = q.gu, Q12 = q.gv, Q13 = T(0);   // at (b, d)
+        Q10 = atBC ? q.gu : Q10; Q11 = atBC ? q.gx : Q11; Q12 = atBC ? T(0) : Q12; Q13 = atBC ? -q.gv : Q13;
+        Q10 = atAD ? q.gv : Q10; Q11 = atAD ? T(0) : Q11; Q12 = atAD ? -q.gx : Q12; Q13 = atAD ? -q.gu : Q13;
+        Q10 = edge ? Qe[0] : Q10; Q11 = edge ? Qe[1] : Q11; Q12 = edge ? Qe[2] : Q12; Q13 = edge ? Qe[3] : Q13;
         // s1 - s0 from the quantity that is exactly zero at one end
-        const T dl = kind0 == KEDGE ? (edge ? q.two_r0m1 + T(2 * m) : (atAD ? -Q01 : atBC ? -Q02 : -Q03))
-                                    : (kind0 == KAC ? Q10 : kind0 == KAD ? Q11 : Q12);
+        T dlc = k0a ? Q11 : Q10;   // from a corner: its offset at s1
+        dlc = k0b ? Q12 : dlc;
+        T dle = atBC ? -Q02 : -Q03;   // from an edge: the corner's offset at s0, or a whole bin
+        dle = atAD ? -Q01 : dle;
+        dle = edge ? dlE : dle;
+        const T dl = k0e ? dle : dlc;
         // legs of the end points at s1 on their current lines
         const T wh1 = sqrt_t(hiS ? Q11 + q.a2 : Q10 + q.c2);
         const T wl1 = sqrt_t(loA ? Q12 + q.c2 : Q10 + q.a2);
-        const PlSwept<T> H = pl_swept(hiS ? q.d : q.a, s0, dl, wh0, wh1);
-        const PlSwept<T> Lo = pl_swept(loA ? q.b : q.c, s0, dl, wl0, wl1);
+        const PlStep<T> sH = pl_step(hiS ? q.d : q.a, dl, wh0, wh1);
+        const PlStep<T> sL = pl_step(loA ? q.b : q.c, dl, wl0, wl1);
+        // atan x - x and atan x of both steps: the short series unless some
+        // lane of the wave needs the angle halvings (rare: ~1 % of the pieces
+        // on 50 mm geometries), decided once per wave so that the common case
+        // has no divergent branch; both give the same result below kSmall
+        AtanPair<T> aH, aL;
+        if (__any(fmax(sH.x, sL.x) >= AtanMx<T>::kSmall)) {
+            aH = AtanMx<T>::eval(sH.x);
+            aL = AtanMx<T>::eval(sL.x);
+        } else {
+            aH = AtanMx<T>::small(sH.x);
+            aL = AtanMx<T>::small(sL.x);
+        }
+        const PlSwept<T> H = pl_swept(sH, s0, wh0, aH);
+        const PlSwept<T> Lo = pl_swept(sL, s0, wl0, aL);
         const T sh = hiS ? T(-1) : T(1), sl = loA ? T(-1) : T(1);
         th += (double)fma(sh, H.A, sl * Lo.A);
         acc += fma(dl, (T)th, fma(sh, H.C, sl * Lo.C));
         // advance
         Q01 = Q11; Q02 = Q12; Q03 = Q13;
         s0 = Q10 + q.s[0];
-        kind0 = next;
+        k0e = edge;
+        k0a = atAD;
+        k0b = atBC;
         wh0 = atAD ? q.a : wh1;
         wl0 = atBC ? q.c : wl1;
         hiS = hiS || atAD;
         loA = loA || atBC;
-        if (edge || next == KBD) {
+        if (edge || atBD) {
             if (!FROM_FIRST || m >= wlo) sink(m, T(0.5) * wgt * acc);
             acc = T(0);
-            if (next == KBD || m >= me) break;
+            if (atBD || m >= me) break;
             ++m;
         }
     }
