@@ -306,7 +306,7 @@ struct PlQuad {
     T gu, gv, gx;          // b^2 - a^2, d^2 - c^2, gu - gv
     T s[4];                // in-plane squared radius of each corner
     T e[4], twoD[4];       // r_m - D_X = (m - j_X) + e_X;  2 D_X
-    int j[4];
+    T j[4];                // j_X, an integer (exact in T: |j_X| < 2^24)
     int mfirst, mlast;     // bins touched
     T two_r0m1;            // 2 r0 - 1: (r0 + m)^2 - (r0 + m - 1)^2 = two_r0m1 + 2m
 };
@@ -327,7 +327,7 @@ __device__ __forceinline__ void pl_setup(PlQuad<T>& q, double a, double b, doubl
         double D = sqrt64(z2 + s);
         double pos = D - r0;
         double jj = floor(pos + 0.5);
-        q.j[X] = (int)jj;
+        q.j[X] = T(jj);
         q.e[X] = T(jj - pos);
         q.twoD[X] = T(2.0 * D);
         q.s[X] = T(s);
@@ -337,10 +337,12 @@ __device__ __forceinline__ void pl_setup(PlQuad<T>& q, double a, double b, doubl
     q.two_r0m1 = T(2.0 * r0 - 1.0);
 }
 
+// s_m - s_X at the edge of bin m (given as T, an exact integer): the
+// difference m - j_X of two integers below 2^24 is exact in T
 template <class T>
-__device__ __forceinline__ T pl_qedge(const PlQuad<T>& q, int X, int m)
+__device__ __forceinline__ T pl_qedge(const PlQuad<T>& q, int X, T m)
 {
-    T t = T(m - q.j[X]) + q.e[X];
+    T t = (m - q.j[X]) + q.e[X];
     return t * (t + q.twoD[X]);
 }
 
@@ -375,92 +377,43 @@ __device__ __forceinline__ PlSwept<T> pl_swept(const PlStep<T>& st, T s0, T w0, 
     return {fma(s0, at.mx, -st.x * w0 * st.dw), at.a};
 }
 
-// Theta(s) at an edge inside the quadrant's range, for a pass that starts
-// after the quadrant's first bin: the angle between the arc's end points from
-// one atan2 of the chord between them (cancellation free: every difference of
-// nearby squares comes from the corner offsets Q[X] = s - s_X, and the sides
-// b - a and d - c from the FP64 differences of squares, (b^2 - a^2) / (a + b):
-// the FP32 values of a and b far from the voxel's projection (~300 radial
-// steps) would leave their difference ~1e-6 off, and Theta carries that error
-// into every later bin of the pair)
-template <class T>
-__device__ __forceinline__ double pl_arc_angle(const PlQuad<T>& q, bool hiS, bool loA, const T Q[4], T wh, T wl)
-{
-    const T xh = hiS ? wh : q.a, yh = hiS ? q.d : wh;
-    const T xl = loA ? q.b : wl, yl = loA ? wl : q.c;
-    T chx, chy;
-    if (!hiS && !loA) {
-        chx = -sdiv(Q[0], q.a + wl);
-        chy = sdiv(Q[0], wh + q.c);
-    } else if (!hiS) {
-        chx = -sdiv(q.gu, q.a + q.b);
-        chy = sdiv(q.gu, wh + wl);
-    } else if (!loA) {
-        chx = -sdiv(q.gv, wh + wl);
-        chy = sdiv(q.gv, q.c + q.d);
-    } else {
-        chx = sdiv(Q[3], wh + q.b);
-        chy = -sdiv(Q[3], q.d + wl);
-    }
-    return atan2((double)fma(xl, chy, -yl * chx), (double)fma(xl, xh, yl * yh));
-}
-
-// Walk the bins [max(mfirst, wlo), min(mlast, whi)] of a planar quadrant; sink(m, area)
-// receives the area in dr^2 units.  A bin is cut into pieces at the corners
-// a^2 + d^2 (the upper end point moves from the line u = a to v = d), b^2 + c^2
-// (the lower one from v = c to u = b) and b^2 + d^2 (the end), at most three;
-// each piece adds dl Theta(s1) + (corrections of both end points) to twice the
-// bin's area, and Theta is carried from piece to piece by the angles the end
-// points sweep (in FP64), so no piece evaluates an inverse trigonometric
-// function of its own.  The piece's kind of end and its squared-radius offsets
-// are chosen by selects, not branches.  FROM_FIRST: the walk starts at the
-// quadrant's first bin whatever wlo and hands only the bins from wlo on to the
-// sink, so that Theta is carried exactly as in a walk over the whole range
-// (a walk that starts later takes Theta from one atan2, accurate to FP32
-// rounding, but that error then persists over the pair's remaining bins).
-template <bool FROM_FIRST = false, class T, class Sink>
+// Walk the bins of a planar quadrant from its first one, mfirst, to
+// min(mlast, whi), handing those from wlo on to sink(m, area) (area in dr^2
+// units).  A bin is cut into pieces at the corners a^2 + d^2 (the upper end
+// point moves from the line u = a to v = d), b^2 + c^2 (the lower one from
+// v = c to u = b) and b^2 + d^2 (the end), at most three; each piece adds
+// dl Theta(s1) + (corrections of both end points) to twice the bin's area, and
+// Theta is carried from piece to piece by the angles the end points sweep (in
+// FP64), so no piece evaluates an inverse trigonometric function of its own.
+// The walk always starts at the first bin, also when the sink wants later ones
+// only (a later LDS pass, a later time tile): a walk started inside the range
+// would need Theta from one atan2 of the end points, accurate to FP32 rounding,
+// whose error then persists over the pair's remaining bins and leaves a step
+// in f.  The piece's kind of end and its squared-radius offsets are chosen by
+// selects, not branches.
+template <class T, class Sink>
 __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T wgt, Sink& sink)
 {
-    const int mb = FROM_FIRST ? q.mfirst : max(q.mfirst, wlo), me = min(q.mlast, whi);
+    const int mb = q.mfirst, me = min(q.mlast, whi);
     if (mb > me || q.mlast < wlo) return;
     // state at the start of the piece: offsets Q0[X] = s0 - s_X (X = AD, BC, BD),
     // s0, the kind of start, which lines the end points are on, their legs, Theta
-    T Q01, Q02, Q03, s0, wh0, wl0;
-    bool k0e, k0a, k0b;   // the piece starts at a bin edge, at corner (a, d), at (b, c); else at (a, c)
-    bool hiS, loA;
-    double th;
-    if (mb == q.mfirst) {
-        Q01 = -q.gv; Q02 = -q.gu; Q03 = -(q.gu + q.gv);
-        s0 = q.s[0];
-        k0e = k0a = k0b = false;
-        hiS = false;
-        loA = false;
-        wh0 = q.c;
-        wl0 = q.a;
-        // Theta just above the nearest corner (a, c): 0, unless the corner is
-        // the origin (the voxel's projection), where the arc is a quarter circle
-        th = (q.a > T(0) || q.c > T(0)) ? 0.0 : 0.5 * M_PI;
-    } else {
-        T Q[4];
-#pragma unroll
-        for (int X = 0; X < 4; ++X) Q[X] = pl_qedge(q, X, mb - 1);
-        Q01 = Q[1]; Q02 = Q[2]; Q03 = Q[3];
-        s0 = Q[0] + q.s[0];
-        k0e = true;
-        k0a = k0b = false;
-        hiS = Q[1] > T(0);
-        loA = Q[2] > T(0);
-        wh0 = hiS ? sqrt_t(Q[1] + q.a2) : sqrt_t(Q[0] + q.c2);
-        wl0 = loA ? sqrt_t(Q[2] + q.c2) : sqrt_t(Q[0] + q.a2);
-        th = pl_arc_angle(q, hiS, loA, Q, wh0, wl0);
-    }
+    T Q01 = -q.gv, Q02 = -q.gu, Q03 = -(q.gu + q.gv);
+    T s0 = q.s[0], wh0 = q.c, wl0 = q.a;
+    bool k0e = false, k0a = false, k0b = false;   // the piece starts at a bin edge, at corner (a, d),
+                                                  // at (b, c); else at (a, c)
+    bool hiS = false, loA = false;
+    // Theta just above the nearest corner (a, c): 0, unless the corner is the
+    // origin (the voxel's projection), where the arc is a quarter circle
+    double th = (q.a > T(0) || q.c > T(0)) ? 0.0 : 0.5 * M_PI;
     int m = mb;
     T acc = T(0);
     for (int guard = 0; guard < 1 << 20; ++guard) {
+        const T fm = T(m);
         T Qe[4];
 #pragma unroll
-        for (int X = 0; X < 4; ++X) Qe[X] = pl_qedge(q, X, m);
-        const T dlE = q.two_r0m1 + T(2 * m);   // from edge to edge
+        for (int X = 0; X < 4; ++X) Qe[X] = pl_qedge(q, X, fm);
+        const T dlE = fma(T(2), fm, q.two_r0m1);   // from edge to edge: (r0 + m)^2 - (r0 + m - 1)^2
         // the piece ends at the next corner inside the bin, else at its outer
         // edge; every choice below is a chain of selects between values that
         // are all computed (the common case has no divergent branch)
@@ -514,7 +467,7 @@ __device__ __forceinline__ void pl_sweep(const PlQuad<T>& q, int wlo, int whi, T
         hiS = hiS || atAD;
         loA = loA || atBC;
         if (edge || atBD) {
-            if (!FROM_FIRST || m >= wlo) sink(m, T(0.5) * wgt * acc);
+            if (m >= wlo) sink(m, T(0.5) * wgt * acc);
             acc = T(0);
             if (atBD || m >= me) break;
             ++m;

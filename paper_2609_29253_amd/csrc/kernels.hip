@@ -212,9 +212,9 @@ struct PlanarPair {
         fold_line(-L2 - x[1], L2 - x[1], V);
         z2 = x[2] * x[2];
     }
-    // FROM_FIRST: each quadrant is walked from its first bin, only bins from wlo
-    // on reach the sink (see pl_sweep)
-    template <bool FROM_FIRST = false, class Sink>
+    // bins wlo .. whi of each quadrant reach the sink (each quadrant is walked
+    // from its first bin, see pl_sweep)
+    template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
         // the lane's non-empty quadrants first, so lanes step through their k-th
@@ -236,7 +236,7 @@ struct PlanarPair {
             const float w = (i ? U.w[1] : U.w[0]) * (j ? V.w[1] : V.w[0]);
             PlQuad<AT> q;
             pl_setup(q, a, b, c, d, z2, r0);
-            pl_sweep<FROM_FIRST>(q, wlo, whi, (AT)w, sink);
+            pl_sweep(q, wlo, whi, (AT)w, sink);
         }
     }
 };
@@ -328,9 +328,9 @@ struct CylinderPair {
         c = box[(4 + 2 * j) * kThreads]; d = box[(5 + 2 * j) * kThreads];
         w = (double)((1 + ((wbits >> i) & 1)) * (1 + ((wbits >> (2 + j)) & 1)));
     }
-    // (each edge is evaluated on its own, so a walk may start at any bin: no
-    // FROM_FIRST variant is needed)
-    template <bool FROM_FIRST = false, class Sink>
+    // bins wlo .. whi of each quadrant reach the sink; each edge is evaluated
+    // on its own, so the walk starts at max(mfirst, wlo)
+    template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
         // the lane's non-empty quadrants first, so lanes step through their k-th
@@ -547,10 +547,10 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_f
 #pragma unroll
                     for (int v = 0; v < NB; ++v) atomicAdd(&hist[v * tile + (m - tlo)], p0[v] * (double)area);
                 };
-                // planar quadrants are walked from their first bin (their
-                // carried arc angle then matches the brick forward's bit for
+                // planar quadrants are walked from their first bin whatever
+                // the tile (their areas are then the brick forward's bit for
                 // bit); cylinder edges are independent of where a walk starts
-                pair.template sweep<SHAPE == 0>(tlo, thi, sink, P.r0);
+                pair.sweep(tlo, thi, sink, P.r0);
             }
         }
     }
