@@ -563,9 +563,8 @@ def main():
     # ---- roofline of the dominant kernel (the area kernel of A or A^T)
     # the area kernel of A (that of A^T does the same area work and takes the same time)
     dom_ms = main_res["ms_forward"]
-    dom_name = "k_fwd_closed"
-    dom_full = (f"k_fwd_closed<{shape}, {'double' if shape == 1 else 'float'}, {min(B, 8) if B > 1 else 1}, "
-                f"float, 0, false>")
+    dom_name = "k_fwd_wave"
+    dom_full = f"k_fwd_wave<{shape}, {'double' if shape == 1 else 'float'}, {min(B, 8) if B > 1 else 1}, float, 0>"
     area_dtype = "f64" if shape == 1 else "f32"
     evals = main_res["evals_per_volume"] * B
     fl = counter_flops(dom_full, prob.name)

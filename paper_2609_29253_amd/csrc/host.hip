@@ -473,6 +473,7 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         off += nk;
     }
     Lp.nbricks = nbricks;
+    Lp.ncubes = (int)(((grid->n[0] + 3) / 4) * ((grid->n[1] + 3) / 4) * ((grid->n[2] + 3) / 4));
     Lp.mode = p.area_mode;
     Lp.fp64 = p.precision == PAT_FP64;
     Lp.U = p.U;

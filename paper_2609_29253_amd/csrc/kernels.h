@@ -38,6 +38,7 @@ struct LaunchPlan {
     const int32_t* sup_order;   // [nbricks] brick indices in Morton order (the list's brick order)
     int tile, ntiles;       // (transducer, time tile) forward: shells per tile and tiles per transducer
                             // (tile = 0: the brick forward)
+    int ncubes;             // 4 x 4 x 4 voxel cubes (one-wave work-groups of the closed-form forward and adjoint)
 };
 
 hipError_t launch_forward(const LaunchPlan& L, const void* coef, void* sig, int B, hipStream_t s);

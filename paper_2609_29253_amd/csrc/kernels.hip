@@ -2,14 +2,18 @@
 //
 // Forward A (Alg. 1):
 //   1. k_fill            f <- 0  (FP64 fine-bin coefficients, [B][K][Mcount])
-//   (sparse forward: k_support_count / _scan / _write list the voxels that are
-//    nonzero in some volume, and k_fwd_closed strides groups of 256 of them)
-//   2. k_fwd_closed /    one work-group per (voxel brick, chunk of transducers):
-//      k_fwd_quad        for each transducer, every voxel of the brick adds
-//                        p0 * |M_i^m| (Alg. 3, Eq. ui_area) or p0 * dA / r into the
-//                        bin of each surface point (Alg. 2, Eq. def_f_point) of an
-//                        LDS FP64 histogram covering the brick's bin window; the
-//                        window is then added to f with FP64 atomics.
+//   2. k_fwd_wave /      closed form: one work-group of one wave per (4 x 4 x 4
+//      k_fwd_quad        voxel cube, chunk of transducers): for each transducer,
+//                        every voxel of the cube adds p0 * |M_i^m| (Alg. 3, Eq.
+//                        ui_area) into an LDS FP64 histogram covering the cube's
+//                        bin window, which the wave then adds to f with FP64
+//                        atomics, with no work-group barrier.  Quadrature: one
+//                        256-thread work-group per (voxel brick, chunk), p0 * dA / r
+//                        into the bin of each surface point (Alg. 2, Eq.
+//                        def_f_point).  Sparse forward: k_support_count / _scan /
+//                        _write list the voxels that are nonzero in some volume,
+//                        and k_fwd_sparse strides groups of 256 of them.  Time
+//                        tiles: k_fwd_tile owns a (transducer, tile) of f.
 //   3. k_fir             s_hat[l] = sum_j G[j] scale[m] f[m], m = U l - j (FP64): the
 //                        convolution with h followed by the block average D_U
 //                        (Eq. discrete_conv, Eq. def_downsampling) as one
@@ -19,10 +23,11 @@
 // Adjoint A^T (Alg. 5-7):
 //   1. k_adjw            W[m] = scale[m] sum_l G[U l - m] y[l]: transpose of the
 //                        block average and correlation with the reversed kernel.
-//   2. k_adj_closed /    one work-group per (brick, chunk of transducers): W of
-//      k_adj_quad        the brick's bin window is staged in LDS, every voxel
-//                        gathers sum_m |M_i^m| W[m] (FP32 or FP64 per transducer)
-//                        and accumulates over transducers in FP64.
+//   2. k_adj_wave /      one work-group per (cube of one wave, or brick for the
+//      k_adj_quad        quadrature, chunk of transducers): W of the bin window is
+//                        staged in LDS, every voxel gathers sum_m |M_i^m| W[m]
+//                        (FP32 or FP64 per transducer) and accumulates over
+//                        transducers in FP64.
 //   3. k_finish          cast of the FP64 sums when transducer chunks were split
 //                        over work-groups.
 #include <hip/hip_runtime.h>
@@ -258,7 +263,7 @@ constexpr int kBoxSlots = 8;
 
 // MERGE of the folded intervals holds for every I_l that is a difference of a
 // function of the end points (exact, tables); not for the chord.
-template <int NW, int IL>
+template <int NW, int IL, int STRIDE = kThreads>   // STRIDE: threads of the work-group (the table's row)
 struct CylinderPair {
     static constexpr bool kMerge = IL != kIlTrapezoid;
     CyPair P;
@@ -316,16 +321,16 @@ struct CylinderPair {
         }
         wbits = (U.w[0] > 1.5f ? 1 : 0) | (U.w[1] > 1.5f ? 2 : 0) | (V.w[0] > 1.5f ? 4 : 0) |
                 (V.w[1] > 1.5f ? 8 : 0);
-        box[0 * kThreads] = U.lo[0]; box[1 * kThreads] = U.hi[0];
-        box[2 * kThreads] = U.lo[1]; box[3 * kThreads] = U.hi[1];
-        box[4 * kThreads] = V.lo[0]; box[5 * kThreads] = V.hi[0];
-        box[6 * kThreads] = V.lo[1]; box[7 * kThreads] = V.hi[1];
+        box[0 * STRIDE] = U.lo[0]; box[1 * STRIDE] = U.hi[0];
+        box[2 * STRIDE] = U.lo[1]; box[3 * STRIDE] = U.hi[1];
+        box[4 * STRIDE] = V.lo[0]; box[5 * STRIDE] = V.hi[0];
+        box[6 * STRIDE] = V.lo[1]; box[7 * STRIDE] = V.hi[1];
     }
     __device__ __forceinline__ void quadrant(int qi, double& a, double& b, double& c, double& d, double& w) const
     {
         const int i = qi >> 1, j = qi & 1;
-        a = box[(2 * i) * kThreads]; b = box[(2 * i + 1) * kThreads];
-        c = box[(4 + 2 * j) * kThreads]; d = box[(5 + 2 * j) * kThreads];
+        a = box[(2 * i) * STRIDE]; b = box[(2 * i + 1) * STRIDE];
+        c = box[(4 + 2 * j) * STRIDE]; d = box[(5 + 2 * j) * STRIDE];
         w = (double)((1 + ((wbits >> i) & 1)) * (1 + ((wbits >> (2 + j)) & 1)));
     }
     // bins wlo .. whi of each quadrant reach the sink; each edge is evaluated
@@ -354,10 +359,12 @@ template <> struct CylNewton<float> { static constexpr int value = 1; };
 
 // IL: how the cylinder's I_l is evaluated (kIlExact, kIlTrapezoid, kIlTable);
 // the planar I_l is exact either way
-template <int SHAPE, class AT, class Real, int IL> struct PairOf;
-template <class AT, class Real, int IL> struct PairOf<0, AT, Real, IL> { using type = PlanarPair<AT>; };
-template <class AT, class Real, int IL> struct PairOf<1, AT, Real, IL> {
-    using type = CylinderPair<CylNewton<Real>::value, IL>;
+template <int SHAPE, class AT, class Real, int IL, int STRIDE = kThreads> struct PairOf;
+template <class AT, class Real, int IL, int STRIDE> struct PairOf<0, AT, Real, IL, STRIDE> {
+    using type = PlanarPair<AT>;
+};
+template <class AT, class Real, int IL, int STRIDE> struct PairOf<1, AT, Real, IL, STRIDE> {
+    using type = CylinderPair<CylNewton<Real>::value, IL, STRIDE>;
 };
 
 // ---------------------------------------------------------------------------
@@ -432,44 +439,38 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
 constexpr int kSparseChunk = 16;
 constexpr int kSparseGrid = 4096;
 
-// Dense: work-group (brick, chunk of transducers).  SPARSE: the work items
-// (group of 256 support entries, chunk of P.kchunk transducers) are strided over
-// a fixed grid, since the number of groups is known on the device only.
-// waves per SIMD the closed-form kernels are built for.  Cylinders for one or
-// two volumes: four, in 128 VGPRs with a few spills outside the sweep, and a
-// 16 KB histogram so that four work-groups share a CU (2 % faster than three
-// on the 128^3 x 256-cylinder workload); with more volumes, and in the sparse
-// forward, the spills grow (120-210 bytes per lane) and they keep three.  The
-// planar sweep in FP64 for four or eight volumes spills 300 bytes per lane at
-// three and runs faster at two (1.75x for the adjoint of eight volumes); for
-// one volume three is faster despite its spills (9 %).
+// Waves per SIMD the closed-form kernels are built for (one-wave work-groups in
+// the dense forward and the adjoint, 256-thread ones in the sparse forward and
+// the time tiles).  Cylinders for one or two volumes: four, in 128 VGPRs with a
+// few spills outside the sweep; with more volumes, and in the sparse forward,
+// the spills grow (120-210 bytes per lane) and they keep three.  The planar
+// sweep in FP64 for four or eight volumes spills 300 bytes per lane at three
+// and runs faster at two (1.75x for the adjoint of eight volumes); for one
+// volume three is faster despite its spills (9 %).  The FP32 planar kernels fit
+// four waves without spills (112-125 VGPRs).
 template <int SHAPE, class AT, int NB, bool SPARSE = false>
 constexpr int closed_waves()
 {
     return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 ? (NB >= 4 ? 2 : 3) : (NB <= 2 ? 4 : 3));
 }
 
-// LDS histogram entries per work-group: 16 KB in FP64 at four waves (four
-// work-groups per CU with the 16 KB interval table), 32 KB otherwise
-template <int SHAPE, class AT, int NB, bool SPARSE = false>
-constexpr int closed_hist()
+// LDS histogram entries of a sparse-forward work-group: 16 KB in FP64 at four
+// waves, 32 KB otherwise
+template <int SHAPE, class AT, int NB>
+constexpr int sparse_hist()
 {
-    return closed_waves<SHAPE, AT, NB, SPARSE>() == 4 ? kHistCyl : kHistTotal;
+    return closed_waves<SHAPE, AT, NB, true>() == 4 ? kHistCyl : kHistTotal;
 }
 
-template <int SHAPE, class AT, int NB, class Real, int IL, bool SPARSE>
-__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) void k_fwd_closed(KParams P, const Real* __restrict__ coef,
-                                                          double* __restrict__ f)
+// Sparse forward: the work items (group of 256 support entries, chunk of
+// P.kchunk transducers) are strided over a fixed grid, since the number of
+// groups is known on the device only.
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, true>())) void k_fwd_sparse(
+    KParams P, const Real* __restrict__ coef, double* __restrict__ f)
 {
-    extern __shared__ double hist[];   // [NB][closed_hist<SHAPE, AT, NB, SPARSE>() / NB]
+    extern __shared__ double hist[];   // [NB][sparse_hist<SHAPE, AT, NB>() / NB]
     __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
-    if (!SPARSE) {
-        Brick Bk;
-        brick_setup(P, blockIdx.x, Bk);
-        const int kbeg = blockIdx.y * P.kchunk;
-        fwd_brick<SHAPE, AT, NB, Real, IL, closed_hist<SHAPE, AT, NB, SPARSE>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
-        return;
-    }
     const int64_t total = *P.sup_total;
     const int64_t nchunks = (P.nk + P.kchunk - 1) / P.kchunk;
     const int64_t items = (total + kThreads - 1) / kThreads * nchunks;
@@ -477,7 +478,110 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, SPARSE>())) 
         Brick Bk;
         brick_setup_sparse(P, it / nchunks, total, Bk);
         const int kbeg = (int)(it % nchunks) * P.kchunk;
-        fwd_brick<SHAPE, AT, NB, Real, IL, closed_hist<SHAPE, AT, NB, SPARSE>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk), coef, f, hist, box);
+        fwd_brick<SHAPE, AT, NB, Real, IL, sparse_hist<SHAPE, AT, NB>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk),
+                                                                          coef, f, hist, box);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward, closed-form areas, one wave per work-group
+// ---------------------------------------------------------------------------
+
+constexpr int kWave = 64;          // threads of a one-wave work-group: a 4 x 4 x 4 voxel cube
+
+// LDS window of a one-wave work-group, in bytes, shared by its volumes: with
+// sixteen of them per CU (four waves per SIMD) each may hold 10 KB; the
+// cylinder kernels also keep their 4 KB table of interval ends there
+template <int SHAPE>
+constexpr int wave_window_bytes()
+{
+    return SHAPE == 1 ? 4096 : 8192;
+}
+
+// One work-group of one wave per (4 x 4 x 4 voxel cube, chunk of transducers).
+// The wave owns its LDS window: it clears it, sweeps into it and adds it to f
+// with no work-group barrier, only the ordering of its own LDS operations.
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_wave(KParams P,
+                                                                                     const Real* __restrict__ coef,
+                                                                                     double* __restrict__ f)
+{
+    constexpr int HE = wave_window_bytes<SHAPE>() / (int)sizeof(double);
+    __shared__ double hist[HE];          // [NB][HW]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kWave : 1];
+    constexpr int HW = HE / NB;          // shells per pass
+    const int ncx = (int)((P.n[0] + 3) / 4), ncy = (int)((P.n[1] + 3) / 4);
+    const int cid = blockIdx.x;
+    const int x0 = (cid % ncx) * 4, y0 = ((cid / ncx) % ncy) * 4, z0 = (cid / (ncx * ncy)) * 4;
+    const int l = threadIdx.x;
+    const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
+    const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
+    const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
+    double lo3[3], hi3[3];
+    {
+        const int x1 = (int)min((int64_t)(x0 + 4), P.n[0]) - 1;
+        const int y1 = (int)min((int64_t)(y0 + 4), P.n[1]) - 1;
+        const int z1 = (int)min((int64_t)(z0 + 4), P.n[2]) - 1;
+        lo3[0] = P.origin[0] + x0 * P.w; hi3[0] = P.origin[0] + x1 * P.w;
+        lo3[1] = P.origin[1] + y0 * P.w; hi3[1] = P.origin[1] + y1 * P.w;
+        lo3[2] = P.origin[2] + z0 * P.w; hi3[2] = P.origin[2] + z1 * P.w;
+    }
+    double p0[NB];
+    bool nz = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        p0[b] = valid ? (double)coef[b * P.N + idx] : 0.0;
+        nz |= p0[b] != 0.0;
+    }
+    if (!__any(nz)) return;
+    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    const int S = P.step;
+    const int64_t Mhi = P.Mlo + P.Mcount - 1;
+    for (int kk = kbeg; kk < kend; ++kk) {
+        const int k = P.kperm[kk];
+        int wlo, whi;
+        typename PairOf<SHAPE, AT, Real, IL, kWave>::type pair;
+        pair.bind(box, P.lut);
+        {
+            const TrDev T = P.tr[k];
+            box_window(P, lo3, hi3, T, wlo, whi);
+            double x[3];
+            frame_coords(T, ix, iy, iz, x);
+            pair.setup(T, x, P.r0);
+        }
+        for (int plo = wlo; plo <= whi; plo += HW) {
+            const int phi = min(whi, plo + HW - 1);
+            const int wn = phi - plo + 1;
+            for (int i = l; i < wn; i += kWave)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) hist[b * HW + i] = 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (nz) {
+                auto sink = [&](int m, auto area) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * HW + (m - plo)], p0[b] * (double)area);
+                };
+                pair.sweep(plo, phi, sink, P.r0);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = l; i < wn * S; i += kWave) {
+                const int jj = i / S;
+                const int64_t m = (int64_t)(plo + jj - 1) * S + 1 + (i - jj * S);
+                if (m < P.Mlo || m > Mhi) continue;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    double v = hist[b * HW + jj];
+                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + (m - P.Mlo)], v * S);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
@@ -595,53 +699,76 @@ __global__ __launch_bounds__(kThreads) void k_tile_cost(KParams P, int nbricks, 
 // adjoint, closed-form areas
 // ---------------------------------------------------------------------------
 
+// One work-group of one wave per (4 x 4 x 4 voxel cube, chunk of transducers):
+// the wave stages its own window of W in LDS and gathers, with no work-group
+// barrier, only the ordering of its own LDS operations.
 template <int SHAPE, class AT, int NB, class Real, int IL>
-__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_adj_closed(KParams P, const Real* __restrict__ W,
-                                                          Real* __restrict__ out, double* __restrict__ z64,
-                                                          int direct)
+__global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_adj_wave(KParams P,
+                                                                                     const Real* __restrict__ W,
+                                                                                     Real* __restrict__ out,
+                                                                                     double* __restrict__ z64,
+                                                                                     int direct)
 {
-    constexpr int HB = closed_hist<SHAPE, AT, NB>() / NB;   // shells per pass
-    extern __shared__ double smem_d[];
-    Real* Ws = reinterpret_cast<Real*>(smem_d);   // [NB][HB]
-    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
-    Brick Bk;
-    brick_setup(P, blockIdx.x, Bk);
+    constexpr int HE = wave_window_bytes<SHAPE>() / (int)sizeof(Real);
+    __shared__ Real Ws[HE];              // [NB][HB]
+    constexpr int HB = HE / NB;          // shells per pass
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kWave : 1];
+    const int ncx = (int)((P.n[0] + 3) / 4), ncy = (int)((P.n[1] + 3) / 4);
+    const int cid = blockIdx.x;
+    const int x0 = (cid % ncx) * 4, y0 = ((cid / ncx) % ncy) * 4, z0 = (cid / (ncx * ncy)) * 4;
+    const int l = threadIdx.x;
+    const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
+    const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
+    const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
+    double lo3[3], hi3[3];
+    {
+        const int x1 = (int)min((int64_t)(x0 + 4), P.n[0]) - 1;
+        const int y1 = (int)min((int64_t)(y0 + 4), P.n[1]) - 1;
+        const int z1 = (int)min((int64_t)(z0 + 4), P.n[2]) - 1;
+        lo3[0] = P.origin[0] + x0 * P.w; hi3[0] = P.origin[0] + x1 * P.w;
+        lo3[1] = P.origin[1] + y0 * P.w; hi3[1] = P.origin[1] + y1 * P.w;
+        lo3[2] = P.origin[2] + z0 * P.w; hi3[2] = P.origin[2] + z1 * P.w;
+    }
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
     const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
+    const int S = P.step;
+    const int64_t Mhi = P.Mlo + P.Mcount - 1;
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
         int wlo, whi;
-        typename PairOf<SHAPE, AT, Real, IL>::type pair;
+        typename PairOf<SHAPE, AT, Real, IL, kWave>::type pair;
         pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
-            brick_window(P, Bk, T, wlo, whi);
+            box_window(P, lo3, hi3, T, wlo, whi);
             double x[3];
-            frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+            frame_coords(T, ix, iy, iz, x);
             pair.setup(T, x, P.r0);
         }
         for (int plo = wlo; plo <= whi; plo += HB) {
             const int phi = min(whi, plo + HB - 1);
             const int wn = phi - plo + 1;
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // transpose of the even split: each shell gathers its fine bins (Remark 1)
-            const int S = P.step;
-            const int64_t Mhi = P.Mlo + P.Mcount - 1;
-            for (int i = threadIdx.x; i < wn; i += kThreads)
+            for (int i = l; i < wn; i += kWave)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     const Real* Wk = W + ((int64_t)b * P.K + k) * P.Mcount;
-                    double acc = 0.0;
+                    double a = 0.0;
                     for (int t = 0; t < S; ++t) {
                         const int64_t m = (int64_t)(plo + i - 1) * S + 1 + t;
-                        if (m >= P.Mlo && m <= Mhi) acc += (double)Wk[m - P.Mlo];
+                        if (m >= P.Mlo && m <= Mhi) a += (double)Wk[m - P.Mlo];
                     }
-                    Ws[b * HB + i] = (Real)(acc * S);
+                    Ws[b * HB + i] = (Real)(a * S);
                 }
-            __syncthreads();
-            if (Bk.valid) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (valid) {
                 AT part[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) part[b] = AT(0);
@@ -655,11 +782,11 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_a
             }
         }
     }
-    if (!Bk.valid) return;
+    if (!valid) return;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        if (direct) out[b * P.N + Bk.idx] = (Real)acc[b];
-        else unsafeAtomicAdd(&z64[b * P.N + Bk.idx], acc[b]);
+        if (direct) out[b * P.N + idx] = (Real)acc[b];
+        else unsafeAtomicAdd(&z64[b * P.N + idx], acc[b]);
     }
 }
 
@@ -991,15 +1118,40 @@ __global__ __launch_bounds__(256) void k_lut_build(double2* __restrict__ T)
 
 namespace {
 
-template <int SHAPE, class AT, class Real, int IL, bool SPARSE = false>
-hipError_t fwd_closed_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
+template <int SHAPE, class AT, class Real, int IL>
+hipError_t fwd_sparse_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
     constexpr size_t d = sizeof(double);
     switch (nb) {
-    case 1: k_fwd_closed<SHAPE, AT, 1, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 1, SPARSE>() * d, s>>>(P, coef, f); break;
-    case 2: k_fwd_closed<SHAPE, AT, 2, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 2, SPARSE>() * d, s>>>(P, coef, f); break;
-    case 4: k_fwd_closed<SHAPE, AT, 4, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 4, SPARSE>() * d, s>>>(P, coef, f); break;
-    default: k_fwd_closed<SHAPE, AT, 8, Real, IL, SPARSE><<<grid, kThreads, closed_hist<SHAPE, AT, 8, SPARSE>() * d, s>>>(P, coef, f); break;
+    case 1: k_fwd_sparse<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 1>() * d, s>>>(P, coef, f); break;
+    case 2: k_fwd_sparse<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 2>() * d, s>>>(P, coef, f); break;
+    case 4: k_fwd_sparse<SHAPE, AT, 4, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 4>() * d, s>>>(P, coef, f); break;
+    default: k_fwd_sparse<SHAPE, AT, 8, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 8>() * d, s>>>(P, coef, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <int SHAPE, class AT, class Real, int IL>
+hipError_t fwd_wave_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
+{
+    switch (nb) {
+    case 1: k_fwd_wave<SHAPE, AT, 1, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    case 2: k_fwd_wave<SHAPE, AT, 2, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    case 4: k_fwd_wave<SHAPE, AT, 4, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    default: k_fwd_wave<SHAPE, AT, 8, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    }
+    return hipGetLastError();
+}
+
+template <int SHAPE, class AT, class Real, int IL>
+hipError_t adj_wave_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
+                       hipStream_t s)
+{
+    switch (nb) {
+    case 1: k_adj_wave<SHAPE, AT, 1, Real, IL><<<grid, kWave, 0, s>>>(P, W, out, z64, direct); break;
+    case 2: k_adj_wave<SHAPE, AT, 2, Real, IL><<<grid, kWave, 0, s>>>(P, W, out, z64, direct); break;
+    case 4: k_adj_wave<SHAPE, AT, 4, Real, IL><<<grid, kWave, 0, s>>>(P, W, out, z64, direct); break;
+    default: k_adj_wave<SHAPE, AT, 8, Real, IL><<<grid, kWave, 0, s>>>(P, W, out, z64, direct); break;
     }
     return hipGetLastError();
 }
@@ -1029,36 +1181,13 @@ hipError_t fwd_tile_cyl(int mode, int nb, const KParams& P, const int32_t* items
     return fwd_tile_nb<1, double, Real, kIlExact>(nb, P, items, nitems, tile, ntiles, nbricks, coef, f, s);
 }
 
-template <int SHAPE, class AT, class Real, int IL>
-hipError_t adj_closed_nb(int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64, int direct,
-                         hipStream_t s)
-{
-    constexpr size_t d = sizeof(Real);
-    switch (nb) {
-    case 1: k_adj_closed<SHAPE, AT, 1, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 1>() * d, s>>>(P, W, out, z64, direct); break;
-    case 2: k_adj_closed<SHAPE, AT, 2, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 2>() * d, s>>>(P, W, out, z64, direct); break;
-    case 4: k_adj_closed<SHAPE, AT, 4, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 4>() * d, s>>>(P, W, out, z64, direct); break;
-    default: k_adj_closed<SHAPE, AT, 8, Real, IL><<<grid, kThreads, closed_hist<SHAPE, AT, 8>() * d, s>>>(P, W, out, z64, direct); break;
-    }
-    return hipGetLastError();
-}
-
 // cylinder launches by I_l variant: area mode 0 exact, 2 trapezoid, 3 tables
-template <class Real, bool SPARSE>
-hipError_t fwd_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
-{
-    if (mode == 2) return fwd_closed_nb<1, double, Real, kIlTrapezoid, SPARSE>(nb, grid, P, coef, f, s);
-    if (mode == 3) return fwd_closed_nb<1, double, Real, kIlTable, SPARSE>(nb, grid, P, coef, f, s);
-    return fwd_closed_nb<1, double, Real, kIlExact, SPARSE>(nb, grid, P, coef, f, s);
-}
-
 template <class Real>
-hipError_t adj_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* W, Real* out, double* z64,
-                   int direct, hipStream_t s)
+hipError_t fwd_sparse_cyl(int mode, int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    if (mode == 2) return adj_closed_nb<1, double, Real, kIlTrapezoid>(nb, grid, P, W, out, z64, direct, s);
-    if (mode == 3) return adj_closed_nb<1, double, Real, kIlTable>(nb, grid, P, W, out, z64, direct, s);
-    return adj_closed_nb<1, double, Real, kIlExact>(nb, grid, P, W, out, z64, direct, s);
+    if (mode == 2) return fwd_sparse_nb<1, double, Real, kIlTrapezoid>(nb, grid, P, coef, f, s);
+    if (mode == 3) return fwd_sparse_nb<1, double, Real, kIlTable>(nb, grid, P, coef, f, s);
+    return fwd_sparse_nb<1, double, Real, kIlExact>(nb, grid, P, coef, f, s);
 }
 
 template <class AT, class Real>
@@ -1141,10 +1270,15 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
                                                          fb, s);
             else if (tiles)
                 e = fwd_tile_cyl<Real>(L.mode, nb, P, G.items, G.nitems, L.tile, L.ntiles, L.nbricks, cb, fb, s);
-            else if (sparse && G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact, true>(nb, grid, P, cb, fb, s);
-            else if (sparse) e = fwd_cyl<Real, true>(L.mode, nb, grid, P, cb, fb, s);
-            else if (G.shape == 0) e = fwd_closed_nb<0, Real, Real, kIlExact>(nb, grid, P, cb, fb, s);
-            else e = fwd_cyl<Real, false>(L.mode, nb, grid, P, cb, fb, s);
+            else if (sparse && G.shape == 0) e = fwd_sparse_nb<0, Real, Real, kIlExact>(nb, grid, P, cb, fb, s);
+            else if (sparse) e = fwd_sparse_cyl<Real>(L.mode, nb, grid, P, cb, fb, s);
+            else {
+                const dim3 gw((unsigned)L.ncubes, (G.nk + G.kchunk_fwd - 1) / G.kchunk_fwd);
+                if (G.shape == 0) e = fwd_wave_nb<0, Real, Real, kIlExact>(nb, gw, P, cb, fb, s);
+                else if (L.mode == 2) e = fwd_wave_nb<1, double, Real, kIlTrapezoid>(nb, gw, P, cb, fb, s);
+                else if (L.mode == 3) e = fwd_wave_nb<1, double, Real, kIlTable>(nb, gw, P, cb, fb, s);
+                else e = fwd_wave_nb<1, double, Real, kIlExact>(nb, gw, P, cb, fb, s);
+            }
             if (e != hipSuccess) return e;
         }
         b0 += nb;
@@ -1184,8 +1318,13 @@ hipError_t adjoint_t(const LaunchPlan& L, const Real* sig, Real* coef, int B, hi
             Real* ob = coef + (int64_t)b0 * P.N;
             double* zb = L.z64 + (int64_t)b0 * P.N;
             if (L.mode == 1) e = adj_quad_nb<Real, Real>(nb, grid, P, Wb, ob, zb, direct, s);
-            else if (G.shape == 0) e = adj_closed_nb<0, Real, Real, kIlExact>(nb, grid, P, Wb, ob, zb, direct, s);
-            else e = adj_cyl<Real>(L.mode, nb, grid, P, Wb, ob, zb, direct, s);
+            else {
+                const dim3 gw((unsigned)L.ncubes, (G.nk + G.kchunk_adj - 1) / G.kchunk_adj);
+                if (G.shape == 0) e = adj_wave_nb<0, Real, Real, kIlExact>(nb, gw, P, Wb, ob, zb, direct, s);
+                else if (L.mode == 2) e = adj_wave_nb<1, double, Real, kIlTrapezoid>(nb, gw, P, Wb, ob, zb, direct, s);
+                else if (L.mode == 3) e = adj_wave_nb<1, double, Real, kIlTable>(nb, gw, P, Wb, ob, zb, direct, s);
+                else e = adj_wave_nb<1, double, Real, kIlExact>(nb, gw, P, Wb, ob, zb, direct, s);
+            }
             if (e != hipSuccess) return e;
         }
         b0 += nb;
