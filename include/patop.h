@@ -170,7 +170,11 @@ pat_status pat_set_geometry(pat_ctx* ctx, const pat_transducer* tr, int32_t K,
                             const pat_params* params);
 
 /* signal = A coef (Alg. 1).  coef: device [batch][N], signal: device
- * [batch][K][L], element type per params.precision.  1 <= batch <= max_batch. */
+ * [batch][K][L], element type per params.precision, each aligned to its element
+ * size.  1 <= batch <= max_batch.  Asynchronous on hip_stream (NULL: the
+ * default stream).  Errors (nothing is launched): PAT_E_ARG for a NULL or
+ * misaligned buffer or a batch out of range, PAT_E_STATE before a successful
+ * pat_set_geometry; PAT_E_DEVICE if a launch fails. */
 pat_status pat_forward(pat_ctx* ctx, const void* coef, void* signal, int32_t batch,
                        void* hip_stream);
 

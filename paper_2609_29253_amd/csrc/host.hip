@@ -568,11 +568,19 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
 
 enum class Op { forward, forward_sparse, adjoint };
 
+// device buffers must hold whole elements of the context's precision
+static bool aligned(const pat_ctx* c, const void* p)
+{
+    const uintptr_t a = c->precision == PAT_FP64 ? sizeof(double) : sizeof(float);
+    return reinterpret_cast<uintptr_t>(p) % a == 0;
+}
+
 static pat_status run(pat_ctx* c, const void* in, void* out, int32_t batch, void* stream, Op op)
 {
     if (!c) return PAT_E_ARG;
     if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
     if (!in || !out || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
+    if (!aligned(c, in) || !aligned(c, out)) return fail(c, PAT_E_ARG, "buffer not aligned to its element size");
     if (op == Op::forward_sparse && c->mode == PAT_AREA_QUADRATURE)
         return fail(c, PAT_E_UNSUPPORTED, "the sparse forward serves the surface methods");
     DevGuard guard(c->device);
@@ -608,6 +616,7 @@ pat_status pat_forward_noalloc(pat_ctx* c, const void* coef, void* signal, int32
     if (!c) return PAT_E_ARG;
     if (!c->ready) return fail(c, PAT_E_STATE, "set_geometry has not succeeded");
     if (!coef || !signal || batch < 1 || batch > c->max_batch) return fail(c, PAT_E_ARG, "null buffer or bad batch");
+    if (!aligned(c, coef) || !aligned(c, signal)) return fail(c, PAT_E_ARG, "buffer not aligned to its element size");
     const double need = (double)batch * c->K * (double)c->plan.base.Mcount * sizeof(double);
     if (need > (double)kScratchBytes) {
         char buf[200];
