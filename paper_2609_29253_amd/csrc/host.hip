@@ -296,7 +296,10 @@ pat_status pat_set_geometry(pat_ctx* c, const pat_transducer* tr, int32_t K, con
         for (int a = 0; a < 3; ++a) d.cen[a] = cen[a] / da;
         d.rad = rad / da;
         if (t.shape == PAT_PLANAR) { d.p[0] = t.half_w / da; d.p[1] = t.half_h / da; }
-        else { d.p[0] = t.radius / da; d.p[1] = t.theta_max; d.p[2] = t.half_len / da; }
+        else {
+            d.p[0] = t.radius / da; d.p[1] = t.theta_max; d.p[2] = t.half_len / da;
+            d.cth = std::cos(t.theta_max); d.sth = std::sin(t.theta_max);
+        }
         d.shape = t.shape;
         double far2 = 0.0;
         for (int a = 0; a < 3; ++a) {

@@ -154,6 +154,54 @@ __device__ __forceinline__ void brick_window(const KParams& P, const Brick& Bk, 
     box_window(P, Bk.lo, Bk.hi, T, wlo, whi);
 }
 
+// shells that the voxel at frame coordinates x can reach on transducer T: from
+// its distances to the nearest and the farthest point of the surface (Eq.
+// rmin_rmax), in closed form.  Planar: the rectangle's nearest and farthest
+// points in its plane.  Cylinder: |x - y|^2 = R^2 + rho^2 - 2 R rho cos(delta)
+// + (z - x3)^2 for the point y at angle gap delta from the voxel's direction,
+// whose smallest gap is 0 inside the angular range and |theta_i| - theta_max
+// outside it, and largest min(pi, |theta_i| + theta_max); rho cos(delta) from
+// the frame coordinates and cos / sin of theta_max, with no angle computed.
+// floor / ceil keep a shell of margin for rounding: [lo, hi] holds every bin of
+// every quadrant sweep of the pair.
+__device__ __forceinline__ void pair_range(const TrDev& T, const double x[3], double r0, int& lo, int& hi)
+{
+    double dmin2, dmax2;
+    if (T.shape == 0) {
+        const double du = fmax(0.0, fabs(x[0]) - T.p[0]), dv = fmax(0.0, fabs(x[1]) - T.p[1]);
+        const double eu = fabs(x[0]) + T.p[0], ev = fabs(x[1]) + T.p[1];
+        const double z2 = x[2] * x[2];
+        dmin2 = fma(du, du, fma(dv, dv, z2));
+        dmax2 = fma(eu, eu, fma(ev, ev, z2));
+    } else {
+        const double R = T.p[0], ax1 = fabs(x[1]);
+        const double rho2 = fma(x[0], x[0], x[1] * x[1]);
+        const double rho = sqrt(rho2);
+        const bool inside = fma(x[0], T.sth, -ax1 * T.cth) >= 0.0;   // |theta_i| <= theta_max
+        const double cmin = inside ? rho : fma(x[0], T.cth, ax1 * T.sth);
+        const double cmax = x[0] < -T.cth * rho ? -rho : fma(x[0], T.cth, -ax1 * T.sth);
+        const double vmin = fmax(0.0, fabs(x[2]) - T.p[2]), vmax = fabs(x[2]) + T.p[2];
+        const double base = fma(R, R, rho2);
+        dmin2 = fma(vmin, vmin, fma(-2.0 * R, cmin, base));
+        dmax2 = fma(vmax, vmax, fma(-2.0 * R, cmax, base));
+    }
+    lo = (int)floor(sqrt(fmax(dmin2, 0.0)) - r0);
+    hi = (int)ceil(sqrt(fmax(dmax2, 0.0)) - r0) + 1;
+}
+
+// [min lo, max hi] over the lanes of the wave that take part (others pass
+// INT_MAX / INT_MIN), clipped to the kept shells [Jlo, Jhi]
+__device__ __forceinline__ void wave_window(const KParams& P, int lo, int hi, int& wlo, int& whi)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    wlo = (int)max((int64_t)lo, P.Jlo);
+    whi = (int)min((int64_t)hi, P.Jhi);
+}
+
 // frame coordinates of a voxel (Sec. 4.1 / Sec. 4.2 frames), FP64
 __device__ __forceinline__ void frame_coords(const TrDev& T, int ix, int iy, int iz, double x[3])
 {
@@ -517,15 +565,6 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_
     const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
     const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
     const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
-    double lo3[3], hi3[3];
-    {
-        const int x1 = (int)min((int64_t)(x0 + 4), P.n[0]) - 1;
-        const int y1 = (int)min((int64_t)(y0 + 4), P.n[1]) - 1;
-        const int z1 = (int)min((int64_t)(z0 + 4), P.n[2]) - 1;
-        lo3[0] = P.origin[0] + x0 * P.w; hi3[0] = P.origin[0] + x1 * P.w;
-        lo3[1] = P.origin[1] + y0 * P.w; hi3[1] = P.origin[1] + y1 * P.w;
-        lo3[2] = P.origin[2] + z0 * P.w; hi3[2] = P.origin[2] + z1 * P.w;
-    }
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -544,9 +583,11 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_
         pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
-            box_window(P, lo3, hi3, T, wlo, whi);
             double x[3];
             frame_coords(T, ix, iy, iz, x);
+            int lo = 0x7fffffff, hi = -0x7fffffff - 1;
+            if (nz) pair_range(T, x, P.r0, lo, hi);   // lanes whose volumes are all zero add nothing
+            wave_window(P, lo, hi, wlo, whi);
             pair.setup(T, x, P.r0);
         }
         for (int plo = wlo; plo <= whi; plo += HW) {
@@ -720,15 +761,6 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_adj_
     const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
     const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
     const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
-    double lo3[3], hi3[3];
-    {
-        const int x1 = (int)min((int64_t)(x0 + 4), P.n[0]) - 1;
-        const int y1 = (int)min((int64_t)(y0 + 4), P.n[1]) - 1;
-        const int z1 = (int)min((int64_t)(z0 + 4), P.n[2]) - 1;
-        lo3[0] = P.origin[0] + x0 * P.w; hi3[0] = P.origin[0] + x1 * P.w;
-        lo3[1] = P.origin[1] + y0 * P.w; hi3[1] = P.origin[1] + y1 * P.w;
-        lo3[2] = P.origin[2] + z0 * P.w; hi3[2] = P.origin[2] + z1 * P.w;
-    }
     double acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -742,9 +774,11 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_adj_
         pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
-            box_window(P, lo3, hi3, T, wlo, whi);
             double x[3];
             frame_coords(T, ix, iy, iz, x);
+            int lo = 0x7fffffff, hi = -0x7fffffff - 1;
+            if (valid) pair_range(T, x, P.r0, lo, hi);
+            wave_window(P, lo, hi, wlo, whi);
             pair.setup(T, x, P.r0);
         }
         for (int plo = wlo; plo <= whi; plo += HB) {

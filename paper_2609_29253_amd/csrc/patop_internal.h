@@ -36,6 +36,7 @@ struct TrDev {
     double cen[3];      // centre of the bounding sphere, global coordinates
     double rad;         // bounding-sphere radius
     double p[3];        // planar: L1, L2, -;  cylinder: R, theta_max, L_z
+    double cth, sth;    // cylinder: cos and sin of theta_max
     int32_t shape;
     int32_t pad;
 };
