@@ -99,30 +99,17 @@ __device__ __forceinline__ void brick_setup(const KParams& P, int bid, Brick& Bk
 
 // Sparse forward: group g is entries 256 g .. 256 g + 255 (< total) of the
 // support list (nonzero voxels listed brick by brick, so they lie in a few
-// neighbouring bricks), one per thread, with the box of those voxels.
+// neighbouring bricks), one per thread; its shell window comes from its pairs'
+// own ranges (pair_range), so it needs no box.
 __device__ __forceinline__ void brick_setup_sparse(const KParams& P, int64_t g, int64_t total, Brick& Bk)
 {
-    __shared__ int bmin[3], bmax[3];
-    const int64_t g0 = g * kThreads;
-    __syncthreads();   // the previous group's box has been read
-    if (threadIdx.x < 3) { bmin[threadIdx.x] = 0x7fffffff; bmax[threadIdx.x] = -1; }
-    __syncthreads();
-    const int64_t e = g0 + threadIdx.x;
+    const int64_t e = g * kThreads + threadIdx.x;
     Bk.valid = e < total;
-    const int64_t idx = P.sup_list[Bk.valid ? e : g0];
+    const int64_t idx = P.sup_list[Bk.valid ? e : g * kThreads];
     Bk.idx = Bk.valid ? idx : 0;
     Bk.ix = (int)(idx % P.n[0]);
     Bk.iy = (int)((idx / P.n[0]) % P.n[1]);
     Bk.iz = (int)(idx / (P.n[0] * P.n[1]));
-    atomicMin(&bmin[0], Bk.ix); atomicMax(&bmax[0], Bk.ix);
-    atomicMin(&bmin[1], Bk.iy); atomicMax(&bmax[1], Bk.iy);
-    atomicMin(&bmin[2], Bk.iz); atomicMax(&bmax[2], Bk.iz);
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        Bk.lo[a] = P.origin[a] + bmin[a] * P.w;
-        Bk.hi[a] = P.origin[a] + bmax[a] * P.w;
-    }
 }
 
 // shells that any voxel of the box [lo, hi] can reach on transducer T
@@ -434,6 +421,7 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
         nz |= p0[b] != 0.0;
     }
     if (!__syncthreads_or(nz)) return;
+    __shared__ int gwin[2];
     for (int kk = kbeg; kk < kend; ++kk) {
         const int k = P.kperm[kk];
         int wlo, whi;
@@ -443,9 +431,24 @@ __device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int
         pair.bind(box, P.lut);
         {
             const TrDev T = P.tr[k];
-            brick_window(P, Bk, T, wlo, whi);
             double x[3];
             frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
+            // the window: the union of the shells the group's pairs reach
+            // (over each wave, then over the group in LDS)
+            int lo = 0x7fffffff, hi = -0x7fffffff - 1;
+            if (nz) pair_range(T, x, P.r0, lo, hi);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                lo = min(lo, __shfl_xor(lo, o));
+                hi = max(hi, __shfl_xor(hi, o));
+            }
+            __syncthreads();   // every thread has read the previous window
+            if (threadIdx.x == 0) { gwin[0] = 0x7fffffff; gwin[1] = -0x7fffffff - 1; }
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) { atomicMin(&gwin[0], lo); atomicMax(&gwin[1], hi); }
+            __syncthreads();
+            wlo = (int)max((int64_t)gwin[0], P.Jlo);
+            whi = (int)min((int64_t)gwin[1], P.Jhi);
             pair.setup(T, x, P.r0);
         }
         for (int plo = wlo; plo <= whi; plo += HB) {
