@@ -187,12 +187,6 @@ __device__ __forceinline__ double rcp_t(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
-template <class T>
-__device__ __forceinline__ T sdiv(T n, T d)
-{
-    return d > T(0) ? n * rcp_t(d) : T(0);
-}
-
 // atan(x) - x and atan(x) for x >= 0, the first without cancellation: halving
 //   atan x - x = 2 (atan y - y) - x^3 / (1 + sqrt(1 + x^2))^2,  y = x / (1 + sqrt(1 + x^2)),
 // (atan x = 2 atan y) then the Taylor series of atan y - y, through y^13; its
@@ -871,9 +865,18 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
         angle_steps(Ea, Eb, dal, dbe);
         sink(m, wR * fma(dal, q.d, fma(-q.c, dbe, Eb.I - Ea.I)));
     };
-    // two shells per trip, the edge records alternating roles (no copies)
+    // two shells per trip, the edge records alternating roles (no copies).
+    // The inner edge of the first bin, r0 + mfirst - 1, does not pass the
+    // nearest corner: both end points sit at u = a and I = 0, so it is set
+    // rather than evaluated (a walk clipped by the window evaluates it)
     CyEdge E0, E1;
-    cy_edge<NW, IL>(q, P, r0 + (mb - 1), E0);
+    if (mb > q.mfirst) {
+        cy_edge<NW, IL>(q, P, r0 + (mb - 1), E0);
+    } else {
+        E0.sa = q.sa; E0.ca = q.ca; E0.da = 1.0;
+        E0.sb = q.sa; E0.cb = q.ca; E0.db = 1.0;
+        E0.I = 0.0;
+    }
     int m = mb;
     for (; m < me; m += 2) {
         cy_edge<NW, IL>(q, P, r0 + m, E1);

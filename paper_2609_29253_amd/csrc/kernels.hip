@@ -345,14 +345,40 @@ struct CylinderPair {
             U.lo[0] = -u2; U.hi[0] = -u1; U.w[0] = 1.0f; U.n = 1;
         }
         fold_line<kMerge>(-Lz - x[2], Lz - x[2], V);
+        // the non-empty quadrants in decreasing order of their number of bins
+        // (nearest to farthest corner, estimated in FP32): the wave steps
+        // through every lane's t-th quadrant together, so the lanes' longest
+        // sweeps share one trip count
+        bool ok[4];
+        float len[4];
+        {
+            const float muf = (float)P.mu, dm2 = (float)(P.dm * P.dm);
+            float pa[2], pb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const float sa = __sinf(0.5f * (float)(i < U.n ? U.lo[i] : 0.0));
+                const float sb = __sinf(0.5f * (float)(i < U.n ? U.hi[i] : 0.0));
+                pa[i] = fmaf(muf * sa, sa, dm2);
+                pb[i] = fmaf(muf * sb, sb, dm2);
+            }
+#pragma unroll
+            for (int qi = 0; qi < 4; ++qi) {
+                const int i = qi >> 1, j = qi & 1;
+                ok[qi] = i < U.n && j < V.n && (i ? U.hi[1] > U.lo[1] : U.hi[0] > U.lo[0]) &&
+                         (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
+                const float c = (float)(j < V.n ? V.lo[j] : 0.0), d = (float)(j < V.n ? V.hi[j] : 0.0);
+                len[qi] = ok[qi] ? fmaxf(sqrt_t(fmaf(d, d, pb[i])) - sqrt_t(fmaf(c, c, pa[i])), 0.0f) : -1.0f;
+            }
+        }
         list = 0;
         nq = 0;
 #pragma unroll
         for (int qi = 0; qi < 4; ++qi) {
-            const int i = qi >> 1, j = qi & 1;
-            const bool ok = i < U.n && j < V.n && (i ? U.hi[1] > U.lo[1] : U.hi[0] > U.lo[0]) &&
-                            (j ? V.hi[1] > V.lo[1] : V.hi[0] > V.lo[0]);
-            if (ok) { list |= qi << (2 * nq); ++nq; }
+            int rank = 0;
+#pragma unroll
+            for (int qj = 0; qj < 4; ++qj)
+                rank += (qj != qi) && (len[qj] > len[qi] || (len[qj] == len[qi] && qj < qi));
+            if (ok[qi]) { list |= qi << (2 * rank); ++nq; }
         }
         wbits = (U.w[0] > 1.5f ? 1 : 0) | (U.w[1] > 1.5f ? 2 : 0) | (V.w[0] > 1.5f ? 4 : 0) |
                 (V.w[1] > 1.5f ? 8 : 0);
@@ -373,8 +399,6 @@ struct CylinderPair {
     template <class Sink>
     __device__ __forceinline__ void sweep(int wlo, int whi, Sink& sink, double r0)
     {
-        // the lane's non-empty quadrants first, so lanes step through their k-th
-        // quadrant together
 #pragma unroll 1
         for (int t = 0; t < nq; ++t) {
             double a, b, c, d, w;
