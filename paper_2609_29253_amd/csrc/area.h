@@ -865,28 +865,41 @@ __device__ __forceinline__ void cy_sweep(const CyQuad& q, const CyPair& P, doubl
         angle_steps(Ea, Eb, dal, dbe);
         sink(m, wR * fma(dal, q.d, fma(-q.c, dbe, Eb.I - Ea.I)));
     };
-    // two shells per trip, the edge records alternating roles (no copies).
     // The inner edge of the first bin, r0 + mfirst - 1, does not pass the
-    // nearest corner: both end points sit at u = a and I = 0, so it is set
-    // rather than evaluated (a walk clipped by the window evaluates it)
+    // nearest corner and the outer edge of the last one, r0 + mlast, is past
+    // the farthest: there both end points sit at u = a (resp. u = b) and I = 0,
+    // so these two edges are set rather than evaluated (a walk the window
+    // clips evaluates its end edges).  Every lane's loop is one edge shorter.
+    auto corner_edge = [](double s, double c, CyEdge& E) {
+        E.sa = s; E.ca = c; E.da = 1.0;
+        E.sb = s; E.cb = c; E.db = 1.0;
+        E.I = 0.0;
+    };
     CyEdge E0, E1;
-    if (mb > q.mfirst) {
+    if (mb > q.mfirst)
         cy_edge<NW, IL>(q, P, r0 + (mb - 1), E0);
-    } else {
-        E0.sa = q.sa; E0.ca = q.ca; E0.da = 1.0;
-        E0.sb = q.sa; E0.cb = q.ca; E0.db = 1.0;
-        E0.I = 0.0;
-    }
+    else
+        corner_edge(q.sa, q.ca, E0);
+    const bool tail = me == q.mlast;
+    const int mend = tail ? me - 1 : me;   // the last edge evaluated
+    // two shells per trip, the edge records alternating roles (no copies)
     int m = mb;
-    for (; m < me; m += 2) {
+    for (; m < mend; m += 2) {
         cy_edge<NW, IL>(q, P, r0 + m, E1);
         shell(m, E0, E1);
         cy_edge<NW, IL>(q, P, r0 + (m + 1), E0);
         shell(m + 1, E1, E0);
     }
-    if (m == me) {
+    if (m == mend) {
         cy_edge<NW, IL>(q, P, r0 + m, E1);
         shell(m, E0, E1);
+        if (tail) {
+            corner_edge(q.sb, q.cb, E0);
+            shell(me, E1, E0);
+        }
+    } else if (tail) {
+        corner_edge(q.sb, q.cb, E1);
+        shell(me, E0, E1);
     }
 }
 
