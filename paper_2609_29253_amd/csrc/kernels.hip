@@ -12,7 +12,7 @@
 //                        into the bin of each surface point (Alg. 2, Eq.
 //                        def_f_point).  Sparse forward: k_support_count / _scan /
 //                        _write list the voxels that are nonzero in some volume,
-//                        and k_fwd_sparse strides groups of 256 of them.  Time
+//                        and k_fwd_sparse_wave strides waves of 64 of them.  Time
 //                        tiles: k_fwd_tile owns a (transducer, tile) of f.
 //   3. k_fir             s_hat[l] = sum_j G[j] scale[m] f[m], m = U l - j (FP64): the
 //                        convolution with h followed by the block average D_U
@@ -95,21 +95,6 @@ __device__ __forceinline__ void brick_setup(const KParams& P, int bid, Brick& Bk
     Bk.valid = Bk.ix < P.n[0] && Bk.iy < P.n[1] && Bk.iz < P.n[2];
     Bk.idx = Bk.valid ? Bk.ix + P.n[0] * (Bk.iy + P.n[1] * (int64_t)Bk.iz) : 0;
     brick_box(P, bid, Bk.lo, Bk.hi);
-}
-
-// Sparse forward: group g is entries 256 g .. 256 g + 255 (< total) of the
-// support list (nonzero voxels listed brick by brick, so they lie in a few
-// neighbouring bricks), one per thread; its shell window comes from its pairs'
-// own ranges (pair_range), so it needs no box.
-__device__ __forceinline__ void brick_setup_sparse(const KParams& P, int64_t g, int64_t total, Brick& Bk)
-{
-    const int64_t e = g * kThreads + threadIdx.x;
-    Bk.valid = e < total;
-    const int64_t idx = P.sup_list[Bk.valid ? e : g * kThreads];
-    Bk.idx = Bk.valid ? idx : 0;
-    Bk.ix = (int)(idx % P.n[0]);
-    Bk.iy = (int)((idx / P.n[0]) % P.n[1]);
-    Bk.iz = (int)(idx / (P.n[0] * P.n[1]));
 }
 
 // shells that any voxel of the box [lo, hi] can reach on transducer T
@@ -410,9 +395,9 @@ struct CylinderPair {
     }
 };
 
-// Cylinder areas are FP64 in both variants.  With FP32 input and output the
-// elliptic differences need ~1e-12, and one correction step after v_rsq_f64 /
-// v_rcp_f64 (relative error 2^-48) is enough; the FP64 variant takes two.
+// Cylinder areas are FP64 in both variants.  With FP32 input and output one
+// correction step after the FP32 seeds of the square roots and reciprocals
+// (2^-46 after it) is enough; the FP64 variant takes two after the FP64 ones.
 template <class Real> struct CylNewton { static constexpr int value = 2; };
 template <> struct CylNewton<float> { static constexpr int value = 1; };
 
@@ -430,132 +415,24 @@ template <class AT, class Real, int IL, int STRIDE> struct PairOf<1, AT, Real, I
 // forward, closed-form areas
 // ---------------------------------------------------------------------------
 
-// one brick (or group of support voxels) against transducers kperm[kbeg .. kend)
-template <int SHAPE, class AT, int NB, class Real, int IL, int HT>
-__device__ __forceinline__ void fwd_brick(const KParams& P, const Brick& Bk, int kbeg, int kend,
-                                          const Real* __restrict__ coef, double* __restrict__ f, double* hist,
-                                          double* box)
-{
-    constexpr int HB = HT / NB;   // shells per pass
-    double p0[NB];
-    bool nz = false;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        p0[b] = Bk.valid ? (double)coef[b * P.N + Bk.idx] : 0.0;
-        nz |= p0[b] != 0.0;
-    }
-    if (!__syncthreads_or(nz)) return;
-    __shared__ int gwin[2];
-    for (int kk = kbeg; kk < kend; ++kk) {
-        const int k = P.kperm[kk];
-        int wlo, whi;
-        // the pair's geometry once per transducer; the transducer record is not
-        // needed afterwards
-        typename PairOf<SHAPE, AT, Real, IL>::type pair;
-        pair.bind(box, P.lut);
-        {
-            const TrDev T = P.tr[k];
-            double x[3];
-            frame_coords(T, Bk.ix, Bk.iy, Bk.iz, x);
-            // the window: the union of the shells the group's pairs reach
-            // (over each wave, then over the group in LDS)
-            int lo = 0x7fffffff, hi = -0x7fffffff - 1;
-            if (nz) pair_range(T, x, P.r0, lo, hi);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                lo = min(lo, __shfl_xor(lo, o));
-                hi = max(hi, __shfl_xor(hi, o));
-            }
-            __syncthreads();   // every thread has read the previous window
-            if (threadIdx.x == 0) { gwin[0] = 0x7fffffff; gwin[1] = -0x7fffffff - 1; }
-            __syncthreads();
-            if ((threadIdx.x & 63) == 0) { atomicMin(&gwin[0], lo); atomicMax(&gwin[1], hi); }
-            __syncthreads();
-            wlo = (int)max((int64_t)gwin[0], P.Jlo);
-            whi = (int)min((int64_t)gwin[1], P.Jhi);
-            pair.setup(T, x, P.r0);
-        }
-        for (int plo = wlo; plo <= whi; plo += HB) {
-            const int phi = min(whi, plo + HB - 1);
-            const int wn = phi - plo + 1;
-            for (int i = threadIdx.x; i < wn; i += kThreads)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) hist[b * HB + i] = 0.0;
-            __syncthreads();
-            if (nz) {
-                auto sink = [&](int m, auto area) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) atomicAdd(&hist[b * HB + (m - plo)], p0[b] * (double)area);
-                };
-                pair.sweep(plo, phi, sink, P.r0);
-            }
-            __syncthreads();
-            // shell j holds the fine bins (j - 1) step + 1 .. j step; its area, in
-            // units of (step dr)^2, is split evenly over them (Remark 1): step^2 / step
-            const int S = P.step;
-            const int64_t Mhi = P.Mlo + P.Mcount - 1;
-            for (int i = threadIdx.x; i < wn * S; i += kThreads) {
-                const int jj = i / S;
-                const int64_t m = (int64_t)(plo + jj - 1) * S + 1 + (i - jj * S);
-                if (m < P.Mlo || m > Mhi) continue;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    double v = hist[b * HB + jj];
-                    if (v != 0.0) unsafeAtomicAdd(&f[((int64_t)b * P.K + k) * P.Mcount + (m - P.Mlo)], v * S);
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// sparse forward: transducers per work item and work-groups of the strided grid
-// (16 waves per CU at 256 CUs)
+// sparse forward: transducers per work item, and the strided grid in units of
+// 256 threads (4 x 4096 one-wave work-groups: 64 waves per CU at 256 CUs)
 constexpr int kSparseChunk = 16;
 constexpr int kSparseGrid = 4096;
 
 // Waves per SIMD the closed-form kernels are built for (one-wave work-groups in
-// the dense forward and the adjoint, 256-thread ones in the sparse forward and
-// the time tiles).  Cylinders for one or two volumes: four, in 128 VGPRs with a
-// few spills outside the sweep; with more volumes, and in the sparse forward,
-// the spills grow (120-210 bytes per lane) and they keep three.  The planar
-// sweep in FP64 for four or eight volumes spills 300 bytes per lane at three
-// and runs faster at two (1.75x for the adjoint of eight volumes); for one
-// volume three is faster despite its spills (9 %).  The FP32 planar kernels fit
-// four waves without spills (112-125 VGPRs).
-template <int SHAPE, class AT, int NB, bool SPARSE = false>
+// the dense and sparse forward and the adjoint, 256-thread ones in the time
+// tiles).  Cylinders for one or two volumes: four, in 128 VGPRs with a few
+// spills outside the sweep; with more volumes the spills grow (120-210 bytes
+// per lane) and they keep three.  The planar sweep in FP64 for four or eight
+// volumes spills 300 bytes per lane at three and runs faster at two (1.75x for
+// the adjoint of eight volumes); for one volume three is faster despite its
+// spills (9 %).  The FP32 planar kernels fit four waves without spills
+// (112-125 VGPRs).
+template <int SHAPE, class AT, int NB>
 constexpr int closed_waves()
 {
-    return SHAPE == 1 ? (NB <= 2 && !SPARSE ? 4 : 3) : (sizeof(AT) == 8 ? (NB >= 4 ? 2 : 3) : (NB <= 2 ? 4 : 3));
-}
-
-// LDS histogram entries of a sparse-forward work-group: 16 KB in FP64 at four
-// waves, 32 KB otherwise
-template <int SHAPE, class AT, int NB>
-constexpr int sparse_hist()
-{
-    return closed_waves<SHAPE, AT, NB, true>() == 4 ? kHistCyl : kHistTotal;
-}
-
-// Sparse forward: the work items (group of 256 support entries, chunk of
-// P.kchunk transducers) are strided over a fixed grid, since the number of
-// groups is known on the device only.
-template <int SHAPE, class AT, int NB, class Real, int IL>
-__global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB, true>())) void k_fwd_sparse(
-    KParams P, const Real* __restrict__ coef, double* __restrict__ f)
-{
-    extern __shared__ double hist[];   // [NB][sparse_hist<SHAPE, AT, NB>() / NB]
-    __shared__ double box[SHAPE == 1 ? kBoxSlots * kThreads : 1];
-    const int64_t total = *P.sup_total;
-    const int64_t nchunks = (P.nk + P.kchunk - 1) / P.kchunk;
-    const int64_t items = (total + kThreads - 1) / kThreads * nchunks;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        Brick Bk;
-        brick_setup_sparse(P, it / nchunks, total, Bk);
-        const int kbeg = (int)(it % nchunks) * P.kchunk;
-        fwd_brick<SHAPE, AT, NB, Real, IL, sparse_hist<SHAPE, AT, NB>()>(P, Bk, kbeg, min(P.nk, kbeg + P.kchunk),
-                                                                          coef, f, hist, box);
-    }
+    return SHAPE == 1 ? (NB <= 2 ? 4 : 3) : (sizeof(AT) == 8 ? (NB >= 4 ? 2 : 3) : (NB <= 2 ? 4 : 3));
 }
 
 // ---------------------------------------------------------------------------
@@ -573,25 +450,19 @@ constexpr int wave_window_bytes()
     return SHAPE == 1 ? 4096 : 8192;
 }
 
-// One work-group of one wave per (4 x 4 x 4 voxel cube, chunk of transducers).
-// The wave owns its LDS window: it clears it, sweeps into it and adds it to f
-// with no work-group barrier, only the ordering of its own LDS operations.
+// The wave's 64 voxels (one per lane; `valid` false for lanes without one)
+// against transducers kperm[kbeg .. kend): per transducer the window is the
+// union of the lanes' pair ranges, swept in passes of HW shells.  The wave owns
+// its LDS window: it clears it, sweeps into it and adds it to f with no
+// work-group barrier, only the ordering of its own LDS operations.
 template <int SHAPE, class AT, int NB, class Real, int IL>
-__global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_wave(KParams P,
-                                                                                     const Real* __restrict__ coef,
-                                                                                     double* __restrict__ f)
+__device__ __forceinline__ void fwd_wave_voxels(const KParams& P, int ix, int iy, int iz, bool valid, int64_t idx,
+                                                int kbeg, int kend, const Real* __restrict__ coef,
+                                                double* __restrict__ f, double* hist, double* box)
 {
     constexpr int HE = wave_window_bytes<SHAPE>() / (int)sizeof(double);
-    __shared__ double hist[HE];          // [NB][HW]
-    __shared__ double box[SHAPE == 1 ? kBoxSlots * kWave : 1];
     constexpr int HW = HE / NB;          // shells per pass
-    const int ncx = (int)((P.n[0] + 3) / 4), ncy = (int)((P.n[1] + 3) / 4);
-    const int cid = blockIdx.x;
-    const int x0 = (cid % ncx) * 4, y0 = ((cid / ncx) % ncy) * 4, z0 = (cid / (ncx * ncy)) * 4;
     const int l = threadIdx.x;
-    const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
-    const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
-    const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
     double p0[NB];
     bool nz = false;
 #pragma unroll
@@ -600,7 +471,6 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_
         nz |= p0[b] != 0.0;
     }
     if (!__any(nz)) return;
-    const int kbeg = blockIdx.y * P.kchunk, kend = min(P.nk, kbeg + P.kchunk);
     const int S = P.step;
     const int64_t Mhi = P.Mlo + P.Mcount - 1;
     for (int kk = kbeg; kk < kend; ++kk) {
@@ -650,6 +520,54 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+    }
+}
+
+// Dense forward: one work-group of one wave per (4 x 4 x 4 voxel cube, chunk
+// of transducers).
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_wave(KParams P,
+                                                                                     const Real* __restrict__ coef,
+                                                                                     double* __restrict__ f)
+{
+    __shared__ double hist[wave_window_bytes<SHAPE>() / sizeof(double)];   // [NB][shells per pass]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kWave : 1];
+    const int ncx = (int)((P.n[0] + 3) / 4), ncy = (int)((P.n[1] + 3) / 4);
+    const int cid = blockIdx.x;
+    const int x0 = (cid % ncx) * 4, y0 = ((cid / ncx) % ncy) * 4, z0 = (cid / (ncx * ncy)) * 4;
+    const int l = threadIdx.x;
+    const int ix = x0 + (l & 3), iy = y0 + ((l >> 2) & 3), iz = z0 + (l >> 4);
+    const bool valid = ix < P.n[0] && iy < P.n[1] && iz < P.n[2];
+    const int64_t idx = valid ? ix + P.n[0] * (iy + P.n[1] * (int64_t)iz) : 0;
+    const int kbeg = blockIdx.y * P.kchunk;
+    fwd_wave_voxels<SHAPE, AT, NB, Real, IL>(P, ix, iy, iz, valid, idx, kbeg, min(P.nk, kbeg + P.kchunk), coef, f,
+                                             hist, box);
+}
+
+// Sparse forward: work items (64 consecutive entries of the support list, a
+// chunk of P.kchunk transducers), strided over a fixed grid of one-wave
+// work-groups, since their number is known on the device only.  The list holds
+// the nonzero voxels brick by brick in Morton order and, inside a brick, 4 x 4
+// x 4 cube by cube, so 64 consecutive entries lie in a few neighbouring cubes
+// and their pair ranges overlap.
+template <int SHAPE, class AT, int NB, class Real, int IL>
+__global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_fwd_sparse_wave(
+    KParams P, const Real* __restrict__ coef, double* __restrict__ f)
+{
+    __shared__ double hist[wave_window_bytes<SHAPE>() / sizeof(double)];   // [NB][shells per pass]
+    __shared__ double box[SHAPE == 1 ? kBoxSlots * kWave : 1];
+    const int64_t total = *P.sup_total;
+    const int64_t nchunks = (P.nk + P.kchunk - 1) / P.kchunk;
+    const int64_t items = (total + kWave - 1) / kWave * nchunks;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int64_t g = it / nchunks;
+        const int64_t e = g * kWave + threadIdx.x;
+        const bool valid = e < total;
+        const int64_t idx = valid ? (int64_t)P.sup_list[e] : 0;
+        const int ix = (int)(idx % P.n[0]), iy = (int)((idx / P.n[0]) % P.n[1]), iz = (int)(idx / (P.n[0] * P.n[1]));
+        const int kbeg = (int)(it % nchunks) * P.kchunk;
+        fwd_wave_voxels<SHAPE, AT, NB, Real, IL>(P, ix, iy, iz, valid, idx, kbeg, min(P.nk, kbeg + P.kchunk), coef,
+                                                 f, hist, box);
     }
 }
 
@@ -1182,12 +1100,11 @@ namespace {
 template <int SHAPE, class AT, class Real, int IL>
 hipError_t fwd_sparse_nb(int nb, dim3 grid, const KParams& P, const Real* coef, double* f, hipStream_t s)
 {
-    constexpr size_t d = sizeof(double);
     switch (nb) {
-    case 1: k_fwd_sparse<SHAPE, AT, 1, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 1>() * d, s>>>(P, coef, f); break;
-    case 2: k_fwd_sparse<SHAPE, AT, 2, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 2>() * d, s>>>(P, coef, f); break;
-    case 4: k_fwd_sparse<SHAPE, AT, 4, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 4>() * d, s>>>(P, coef, f); break;
-    default: k_fwd_sparse<SHAPE, AT, 8, Real, IL><<<grid, kThreads, sparse_hist<SHAPE, AT, 8>() * d, s>>>(P, coef, f); break;
+    case 1: k_fwd_sparse_wave<SHAPE, AT, 1, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    case 2: k_fwd_sparse_wave<SHAPE, AT, 2, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    case 4: k_fwd_sparse_wave<SHAPE, AT, 4, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
+    default: k_fwd_sparse_wave<SHAPE, AT, 8, Real, IL><<<grid, kWave, 0, s>>>(P, coef, f); break;
     }
     return hipGetLastError();
 }
@@ -1323,7 +1240,7 @@ hipError_t forward_t(const LaunchPlan& L, const Real* coef, Real* sig, int B, hi
                 P.sup_list = L.sup_list;
                 P.sup_total = L.sup_off + L.nbricks;
                 P.kchunk = kSparseChunk;
-                grid = dim3(kSparseGrid, 1);
+                grid = dim3(kSparseGrid * (kThreads / kWave), 1);
             }
             if (L.mode == 1) e = fwd_quad_nb<Real, Real>(nb, grid, P, cb, fb, s);
             else if (tiles && G.shape == 0)

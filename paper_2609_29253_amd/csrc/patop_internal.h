@@ -19,11 +19,6 @@ constexpr int kBrickY = 8;
 constexpr int kBrickZ = 4;
 static_assert(kBrickX * kBrickY * kBrickZ == kThreads, "one voxel per thread");
 static_assert(kBrickX == 8 && kBrickY == 8 && kBrickZ == 4, "four 4 x 4 x 4 wave sub-cubes per brick");
-constexpr int kHistTotal = 4096;   // LDS window entries per work-group, shared by its volumes:
-                                   // a pass covers kHistTotal / NB shells (32 KB in FP64)
-constexpr int kHistCyl = 2048;     // the same for the cylinder kernels built for four waves per
-                                   // SIMD (16 KB in FP64): with the 16 KB table of interval ends,
-                                   // four work-groups share a CU
 constexpr int kHistQuad = 1024;    // quadrature kernels: bins per pass and volume (their windows
                                    // are narrow and more of them fit a CU with 8 KB each)
 constexpr int kMaxNB = 8;          // volumes per launch
