@@ -132,8 +132,9 @@ def time_op(op, coef, y, steps, warmup, torch):
 
 def run_tiles(prob, torch, dev, log, steps=3):
     """A/B of the forward's two decompositions on the workload (FP32 I/O,
-    closed form): (voxel brick, transducer chunk) work-groups adding into f
-    with atomics, against (transducer, time tile) work-groups that own their
+    closed form): one-wave (4 x 4 x 4 voxel cube, transducer chunk)
+    work-groups adding into f with atomics, against 256-thread (transducer,
+    time tile) work-groups that own their
     tile of f, at the automatic and at fixed tile widths.  Forward time only
     (the adjoint is the same in both), HIP events on torch's current stream."""
     from paper_2609_29253_amd.operator import PatOperator, build_kernel
@@ -159,9 +160,9 @@ def run_tiles(prob, torch, dev, log, steps=3):
         if ref is None:
             ref = out
         diff = float(torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref))
-        row = {"decomposition": "bricks" if tiles is None else "time tiles",
+        row = {"decomposition": "cubes" if tiles is None else "time tiles",
                "tile_shells": int(op.query(9)), "automatic": tiles == 0, "ms_forward": round(ms, 3),
-               "rel_l2_vs_bricks": diff}
+               "rel_l2_vs_cubes": diff}
         rows.append(row)
         log(f"[bench] tiles {prob.name}: {row}")
         op.close()
@@ -249,7 +250,7 @@ def run_lib(torch, dev, log):
     The dense A + A^T at U = 11, area per native sample and per fine bin, on a
     sub-scan of one angle x 5 translations (320 cylinders), scaled by K to the
     whole scan: the operator of the paper's reconstruction.  (The forward skips
-    the all-zero bricks of the sparse phantom by itself; the adjoint covers every
+    the all-zero cubes of the sparse phantom by itself; the adjoint covers every
     voxel.)  Errors against the
     oracle on a few transducers / voxels."""
     import numpy as np
@@ -466,7 +467,7 @@ def main():
                          "384 cylinders, 50 iterations, checkpoints every 10, a resume from iteration 40), "
                          "printed as one JSON object instead of the benchmark line")
     ap.add_argument("--tiles", action="store_true",
-                    help="only the A/B of the forward's decompositions on the workload (voxel bricks against "
+                    help="only the A/B of the forward's decompositions on the workload (voxel cubes against "
                          "(transducer, time tile) work-groups at several tile widths), printed as one JSON "
                          "object instead of the benchmark line")
     ap.add_argument("--pgd-dir", default=None, help="folder for the --pgd checkpoints (default: a temporary one)")

@@ -142,8 +142,8 @@ typedef struct {
 /* pat_params.flags: the closed-form forward (area modes closed, trapezoid and
  * table; not quadrature, where it is refused with PAT_E_ARG) runs one
  * work-group per (transducer, tile of consecutive area shells) that owns its
- * tile of the fine-bin vector f_k (Eq. ui_area), instead of one per (voxel
- * brick, transducer chunk) adding into f with atomics.  Same result to
+ * tile of the fine-bin vector f_k (Eq. ui_area), instead of one per (4 x 4 x
+ * 4 voxel cube, transducer chunk) adding into f with atomics.  Same result to
  * rounding (the order of the FP64 sums differs).  The work items are sorted by
  * an estimated cost at pat_set_geometry; pat_forward_sparse and the adjoint
  * are unchanged.  pat_query(9) returns the tile width (0 when off). */

@@ -37,7 +37,7 @@ struct LaunchPlan {
     int32_t* sup_off;       // [nbricks + 1] their exclusive prefix sums (last entry: total)
     const int32_t* sup_order;   // [nbricks] brick indices in Morton order (the list's brick order)
     int tile, ntiles;       // (transducer, time tile) forward: shells per tile and tiles per transducer
-                            // (tile = 0: the brick forward)
+                            // (tile = 0: the cube forward)
     int ncubes;             // 4 x 4 x 4 voxel cubes (one-wave work-groups of the closed-form forward and adjoint)
 };
 

@@ -638,15 +638,16 @@ __global__ __launch_bounds__(kThreads, (closed_waves<SHAPE, AT, NB>())) void k_f
                     for (int v = 0; v < NB; ++v) atomicAdd(&hist[v * tile + (m - tlo)], p0[v] * (double)area);
                 };
                 // planar quadrants are walked from their first bin whatever
-                // the tile (their areas are then the brick forward's bit for
-                // bit); cylinder edges are independent of where a walk starts
+                // the tile, and a cylinder walk evaluates each edge on its own
+                // (the edges outside its quadrant set as in the cube forward):
+                // the areas are the cube forward's bit for bit
                 pair.sweep(tlo, thi, sink, P.r0);
             }
         }
     }
     __syncthreads();
     // shell j holds the fine bins (j - 1) step + 1 .. j step, its area split
-    // evenly over them (Remark 1), as in the brick kernels
+    // evenly over them (Remark 1), as in the cube forward
     const int S = P.step;
     const int64_t Mhi = P.Mlo + P.Mcount - 1;
     const int wn = thi - tlo + 1;
@@ -1005,9 +1006,10 @@ __global__ __launch_bounds__(kThreads) void k_support_scan(const int32_t* __rest
     if (threadIdx.x == 0) off[n] = carry;
 }
 
-// the nonzero voxels of each brick at the brick's offset, in thread order; bricks
-// in the order `order` (Morton order of the brick coordinates, so that 256
-// consecutive entries lie in a compact cluster of bricks)
+// the nonzero voxels of each brick at the brick's offset, in thread order (the
+// brick's four 4 x 4 x 4 cubes in turn); bricks in the order `order` (Morton
+// order of the brick coordinates, so that consecutive entries lie in a compact
+// cluster of bricks)
 template <class Real>
 __global__ __launch_bounds__(kThreads) void k_support_write(KParams P, const Real* __restrict__ coef, int B,
                                                              const int32_t* __restrict__ order,

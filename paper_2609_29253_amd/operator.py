@@ -86,7 +86,7 @@ class PatOperator:
         p.quad_n1, p.quad_n2 = int(quad_n[0]), int(quad_n[1])
         p.precision = L.PAT_FP32 if precision == "fp32" else L.PAT_FP64
         p.max_batch = self.max_batch
-        # time_tiles: None (brick forward), 0 (time-tile forward, automatic tile
+        # time_tiles: None (cube forward), 0 (time-tile forward, automatic tile
         # width) or the tile width in area shells (a power of two, 32..512)
         if time_tiles is None:
             p.flags = 0

@@ -1,5 +1,5 @@
 """The (transducer, time tile) forward against the FP64 oracle, element by
-element through the C ABI, and against the brick forward.
+element through the C ABI, and against the cube forward.
 
 In this forward one work-group owns a tile of consecutive area shells of one
 transducer's fine-bin vector f_k (Eq. ui_area) and stores it, with no fill and
@@ -11,9 +11,9 @@ right-hand sides), the coarse area grid (a tile of shells is step x tile fine
 bins), both shape groups in one geometry, the trapezoidal and lookup-table
 cylinder I_l, and the refusal of the quadrature mode and of invalid widths.
 
-Bars: those of the brick forward against the oracle (FP32 1e-5 relative L2
-and the per-row bound ROW_TAU, FP64 1e-11).  Against the brick forward: each
-area is evaluated as in the brick forward (a planar quadrant is walked from its
+Bars: those of the cube forward against the oracle (FP32 1e-5 relative L2
+and the per-row bound ROW_TAU, FP64 1e-11).  Against the cube forward: each
+area is evaluated as in the cube forward (a planar quadrant is walked from its
 first bin whatever the tile, a cylinder edge on its own) and the two forwards
 sum the same FP64 terms in other groupings, so FP64 rows agree to 1e-13 of
 their largest sample and FP32 rows to one unit in the last place away from
@@ -47,12 +47,12 @@ def forward_gpu(prob, mode, prec, step, tiles):
     return out, width
 
 
-def brick_agreement(prec, s_tile, s_brick):
+def cube_agreement(prec, s_tile, s_cube):
     """(measure, bar): FP64, the largest per-row difference over the row's
     largest sample; FP32, the largest ulp distance away from zero crossings."""
     if prec == "fp64":
-        return row_ratio(s_tile, s_brick), 1e-13
-    return fp32_repeat_ok(s_tile, s_brick), 1
+        return row_ratio(s_tile, s_cube), 1e-13
+    return fp32_repeat_ok(s_tile, s_cube), 1
 
 
 CASES = [
@@ -75,18 +75,18 @@ def _id(c):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", CASES, ids=_id)
-def test_tiles_against_oracle_and_bricks(gpu, case, prec):
+def test_tiles_against_oracle_and_cubes(gpu, case, prec):
     shape, U, step, B, n, K, L, mode, tile = case
     p = P.small_case(shape, n=n, K=K, U=U, B=B, L=L, seed=4)
     print(f"case {p.name} U={U} step={step} B={B} {mode} tile={tile} {prec}", flush=True)
     s_ref = O.forward(p, mode=OMODE[mode], step=step)
     s, width = forward_gpu(p, mode, prec, step, tile)
     assert width == (tile if tile else width) and 32 <= width <= 512
-    s_brick, off = forward_gpu(p, mode, prec, step, None)
+    s_cube, off = forward_gpu(p, mode, prec, step, None)
     assert off == 0
     e, r = rel_l2(s, s_ref), row_ratio(s, s_ref)
-    agree, bar = brick_agreement(prec, s, s_brick)
-    print(f"  tile {width:.0f}: rel L2 {e:.3e}, worst row {r:.3e}; against the brick forward "
+    agree, bar = cube_agreement(prec, s, s_cube)
+    print(f"  tile {width:.0f}: rel L2 {e:.3e}, worst row {r:.3e}; against the cube forward "
           f"{agree:.3g} (bar {bar:g})", flush=True)
     assert np.linalg.norm(s_ref) > 0
     assert e < TOL[prec] and r <= ROW_TAU[prec]
@@ -101,10 +101,10 @@ def test_tiles_mixed_shapes(gpu, prec, tile):
     p = P.mixed_case(n=13, K_planar=3, K_cyl=3, L=300, seed=2, B=2)
     s_ref = O.forward(p)
     s, width = forward_gpu(p, "closed", prec, 1, tile)
-    s_brick, _ = forward_gpu(p, "closed", prec, 1, None)
+    s_cube, _ = forward_gpu(p, "closed", prec, 1, None)
     e, r = rel_l2(s, s_ref), row_ratio(s, s_ref)
-    agree, bar = brick_agreement(prec, s, s_brick)
-    print(f"mixed tile {width:.0f} {prec}: rel L2 {e:.3e}, worst row {r:.3e}, against bricks {agree:.3g} "
+    agree, bar = cube_agreement(prec, s, s_cube)
+    print(f"mixed tile {width:.0f} {prec}: rel L2 {e:.3e}, worst row {r:.3e}, against cubes {agree:.3g} "
           f"(bar {bar:g})", flush=True)
     assert e < TOL[prec] and r <= ROW_TAU[prec]
     assert agree <= bar
@@ -146,7 +146,7 @@ def row_ratios(got, ref):
 @pytest.mark.parametrize("name,ks", [("cyl256_128c", [0, 131]), ("planar512_256c", [0, 301])])
 def test_tiles_full_size(gpu, name, ks):
     """The benchmark's workloads with the automatic width, FP32 I/O.  Every
-    row against the brick forward; the oracle on two fixed transducers and on
+    row against the cube forward; the oracle on two fixed transducers and on
     the row where the two forwards differ most, over every voxel, where both
     forwards must meet the per-row bound.  Rows agree to one FP32 unit in the
     last place of the row's largest sample: the two forwards sum the same terms
@@ -155,18 +155,18 @@ def test_tiles_full_size(gpu, name, ks):
     lanes that differ between the two."""
     p = {"cyl256_128c": P.cyl256_128c, "planar512_256c": P.planar512_256c}[name]()
     s, width = forward_gpu(p, "closed", "fp32", 1, 0)
-    s_brick, _ = forward_gpu(p, "closed", "fp32", 1, None)
-    d = row_ratios(s, s_brick)
+    s_cube, _ = forward_gpu(p, "closed", "fp32", 1, None)
+    d = row_ratios(s, s_cube)
     worst = int(np.argmax(d))
     check = sorted(set(ks) | {worst})
     s_ref = O.forward(p, ksub=np.asarray(check, dtype=np.int32))
-    got, brick = s[:, check, :], s_brick[:, check, :]
+    got, cube = s[:, check, :], s_cube[:, check, :]
     e, r = rel_l2(got, s_ref), row_ratio(got, s_ref)
-    eb, rb = rel_l2(brick, s_ref), row_ratio(brick, s_ref)
+    eb, rb = rel_l2(cube, s_ref), row_ratio(cube, s_ref)
     bar = 2.0 ** -23
-    print(f"[{name}] tile {width:.0f}: rows against the brick forward: largest difference {d.max():.3e} of the "
+    print(f"[{name}] tile {width:.0f}: rows against the cube forward: largest difference {d.max():.3e} of the "
           f"row maximum (transducer {worst}, bar {bar:.3g}), median {np.median(d):.3e}; oracle on transducers "
-          f"{check}: tile rel L2 {e:.3e}, worst row {r:.3e}; brick rel L2 {eb:.3e}, worst row {rb:.3e}",
+          f"{check}: tile rel L2 {e:.3e}, worst row {r:.3e}; cube rel L2 {eb:.3e}, worst row {rb:.3e}",
           flush=True)
     assert e < TOL["fp32"] and r <= ROW_TAU_FULL["fp32"]
     assert eb < TOL["fp32"] and rb <= ROW_TAU_FULL["fp32"]
