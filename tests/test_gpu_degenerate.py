@@ -1,7 +1,8 @@
 """Degenerate geometries on the GPU against the oracle: voxels on a cylinder's
 focal line (rho = 0, where Phi is always clamped and nu = 0), voxels in the
 plane of a cylinder's axial ends and of a planar rectangle's edges (folded
-intervals that touch 0 or vanish), and voxels on a planar transducer's axis.
+intervals that touch 0 or vanish), voxels on a planar transducer's axis, and
+patches smaller than a fine bin (whole quadrants inside one or two bins).
 The areas are continuous across these boundaries, so the two sides agree to
 rounding even where they round a coordinate to opposite sides of a fold."""
 import math
@@ -46,12 +47,21 @@ def _cases():
         # planar rectangles facing the grid whose edges lie on voxel planes, centred on the z axis
         "planar_edges": _problem([P.planar([0, 0, 3e-3 * g], [1, 0, 0], [0, 1, 0], 0.3e-3, 0.2e-3),
                                   P.planar([0, 0, -3e-3 * g], [0, 1, 0], [1, 0, 0], 0.5e-3, 0.1e-3)], "pl_edges"),
+        # patches of a few tens of micrometres (a bin is 37.5 um): most quadrants lie
+        # inside one or two bins, so a cylinder walk's set first edge (below the nearest
+        # corner) and set last edge (past the farthest) bound a single evaluated edge or
+        # none, and a planar walk crosses all its corners in one bin.  The areas are
+        # differences of squared distances ~(D / a)^2 ~ 1e4 times larger than
+        # themselves (D = 3-4 mm, a = 25-35 um), which FP64 still resolves to ~1e-12
+        "tiny_patches": _problem([P.cylinder([0, 0, 0], z, [1, 0, 0], 4e-3 * g, 8e-3, 25e-6),
+                                  P.cylinder([0, 0, 0.2e-3], [1, 0, 0], [0, 1, 0], 3e-3 * g, 1e-2, 30e-6),
+                                  P.planar([0, 0, 3e-3 * g], [1, 0, 0], [0, 1, 0], 35e-6, 25e-6)], "tiny"),
     }
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("mode", ["closed", "lut"])
-@pytest.mark.parametrize("case", ["cyl_focal_line", "cyl_axis_x", "planar_edges"])
+@pytest.mark.parametrize("case", ["cyl_focal_line", "cyl_axis_x", "planar_edges", "tiny_patches"])
 def test_degenerate_geometry(gpu, case, mode, prec):
     from paper_2609_29253_amd.operator import PatOperator
     p = _cases()[case]
