@@ -142,3 +142,30 @@ def test_sparse_forward_rejects_quadrature(gpu):
         op.forward(torch.tensor(p.coef, dtype=torch.float32, device=gpu), sparse=True)
     assert e.value.status == 9
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("geometry", ["planar", "mixed"])
+def test_sparse_forward_planar_and_mixed(gpu, geometry, prec):
+    """The sparse forward's planar sweep, alone and beside cylinders (two shape
+    groups in one geometry), over a support of about a quarter of the voxels in
+    two volumes, against the dense forward and the oracle."""
+    from paper_2609_29253_amd.operator import PatOperator
+    if geometry == "planar":
+        p = P.small_case(P.PLANAR, n=11, K=5, L=220, B=2, seed=15)
+    else:
+        p = P.mixed_case(n=11, K_planar=3, K_cyl=3, L=300, seed=16, B=2)
+    coef = p.coef.copy()
+    rng = np.random.default_rng(17)
+    coef[rng.random(coef.shape) < 0.75] = 0.0
+    op = PatOperator.from_problem(p, mode="closed", precision=prec, max_batch=2)
+    c = torch.tensor(coef, dtype=DT[prec], device=gpu)
+    s_full = op.forward(c).double().cpu().numpy()
+    s_sp = op.forward(c, sparse=True).double().cpu().numpy()
+    op.close()
+    s_ref = O.forward(p, coef=coef)
+    e_self, e_ref, r_ref = rel_l2(s_sp, s_full), rel_l2(s_sp, s_ref), row_ratio(s_sp, s_ref)
+    print(f"{geometry} {prec}: sparse vs full {e_self:.3e}  vs oracle {e_ref:.3e} (worst row {r_ref:.3e})", flush=True)
+    assert np.linalg.norm(s_ref) > 0
+    assert e_self < SELF[prec] and e_ref < TOL[prec]
+    assert r_ref <= ROW_TAU[prec]
