@@ -774,10 +774,14 @@ __global__ __launch_bounds__(kWave, (closed_waves<SHAPE, AT, NB>())) void k_adj_
 // quadrature over surface points (Alg. 2 / Alg. 6)
 // ---------------------------------------------------------------------------
 
-// bin of the distance sqrt(r2): [r0 + m - 1, r0 + m); FP32 estimate, FP64 decision
+// bin of the distance sqrt(r2): [r0 + m - 1, r0 + m); FP32 estimate, FP64
+// decision.  The estimate is the one v_sqrt_f32 (1 ulp; the correctly rounded
+// sqrtf the compiler would emit costs some 15 more instructions per point): at
+// any distance here it lands within one bin of the true one, which the two FP64
+// comparisons then correct
 __device__ __forceinline__ int point_bin(double r2, double r0, float r0f)
 {
-    float rf = __builtin_sqrtf((float)r2);
+    float rf = __builtin_amdgcn_sqrtf((float)r2);
     int m = (int)floorf(rf - r0f) + 1;
     double e = r0 + (double)(m - 1);
     if (r2 < e * e) return m - 1;
