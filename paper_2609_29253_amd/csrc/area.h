@@ -32,7 +32,7 @@
 // Eq. cyl_Il), in FP64: the cylinder's I_l is a difference of nearly equal
 // elliptic integrals.  E(beta/2, nu) - E(alpha/2, nu) is evaluated by Legendre's
 // addition theorem, E(phi) - E(psi) = E(sigma) - nu sin phi sin psi sin sigma, so
-// only one Carlson evaluation at the small amplitude sigma is needed
+// only one Carlson evaluation, at the amplitude sigma of the difference, is needed
 // (E = s R_F(c^2, 1 - nu s^2, 1) - nu/3 s^3 R_D(c^2, 1 - nu s^2, 1), valid for
 // nu > 1 whenever nu s^2 <= 1, Lemma exact_integral).  The half angles of the
 // clamped inverse Phi (Eq. alphabeta) come from
