@@ -584,10 +584,12 @@ __device__ __forceinline__ void cy_endpoint(const CyQuad& q, const CyPair& P, do
 // nu s^3 R_D(c^2, D^2, 1) / 3 (DLMF 19.25.9), with Carlson's duplication and
 // the series of DLMF 19.36.1-2 through degree 7.  Their truncation error is
 // ~eps^8 / 4 for eps = max |1 - x_i / A|, so the duplication stops once
-// eps < 1/35 (relative error ~1e-13) in the FP64 kernels and once eps < 1/12
-// (~6e-10) in the FP32-I/O ones (NW = 1), whose outputs round at 6e-8: that
-// saves most lanes a duplication step, and on 128^3 voxels x 256 cylinders
-// moves the signals' error against FP64 from 5.7e-8 to 6.9e-8 (relative L2).
+// eps < 1/35 (relative error ~1e-13; 4e-15 measured over amplitudes to 1.55
+// rad and nu sin^2 up to 0.99999) in the FP64 kernels and once eps < 1/12
+// (truncation 2e-11 measured, 5e-10 with the FP32 series terms below) in the
+// FP32-I/O ones (NW = 1), whose outputs round at 6e-8: that saves most lanes a
+// duplication step, and on 128^3 voxels x 256 cylinders moves the signals'
+// error against FP64 from 5.7e-8 to 6.9e-8 (relative L2).
 // TABLE: stop at eps < 1e-4 instead (truncation far below rounding) and also
 // return F = s R_F(c^2, D^2, 1).
 // The duplication runs on 4^n times the n-th iterates: a step then adds
@@ -643,8 +645,8 @@ __device__ __forceinline__ double ellip_e_scd(double s, double c, double dl, dou
     if constexpr (NW == 1) {
         // FP32-I/O kernels: the series' corrections to 1 are O(eps^2) <= ~7e-3
         // (eps < 1/12 at the stop), so FP32 (twice the FP64 rate on gfx950)
-        // leaves ~4e-10 relative error on R_F and R_D, the size of the
-        // truncation; the deviations X, Y themselves are formed in FP64
+        // leaves ~5e-10 relative error on E; the deviations X, Y themselves
+        // are formed in FP64
         const float xf = (float)X, yf = (float)Y, zf = -xf - yf;
         const float e2 = fmaf(xf, yf, -zf * zf), e3 = xf * yf * zf;
         const float df = fmaf(e2, fmaf(e2, fmaf(e2, -5.0f / 208.0f, 1.0f / 24.0f), -0.1f),
